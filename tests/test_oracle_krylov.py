@@ -1,0 +1,113 @@
+"""Pins of oracle/krylov.py (no GPU): exactness, closed forms, special cases,
+linearity and the adaptive controller's accuracy."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed_form, krylov, operators, phi
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("kind", [W.OP_ADR, W.OP_ALLEN_CAHN, W.OP_BRUSSELATOR])
+@pytest.mark.parametrize("orth", ["mgs", "hybrid"])
+def test_exact_when_m_equals_dimension(kind, orth):
+    pr = W.random_problem(41, kind=kind, nx=5, ny=4, p=2, h=0.2, with_diag=True)
+    n = pr.op.n + pr.p
+    ref = phi.phi_combo_dense(operators.dense(pr.op), pr.B, pr.h, pr.p)
+    y, info = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=n, fixed_substeps=1,
+                               m_max=n, orth=orth)
+    assert rel(y, ref) <= 1e-12
+
+
+def test_config1_matches_dft_closed_form():
+    pr = W.config1()
+    y, info = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=40, fixed_substeps=1,
+                               m_max=40)
+    ref = closed_form.adr_phi_combo(pr.op, pr.B, pr.h, pr.p)
+    assert rel(y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_adaptive_meets_tolerance_against_closed_form(tol):
+    op = W.Operator(kind=W.OP_ADR, nx=48, ny=40, nu=0.1, ax=1.0, ay=0.5, react=-0.5)
+    rng = np.random.default_rng(42)
+    B = rng.standard_normal((op.n, 4))
+    h = 0.1
+    ref = closed_form.adr_phi_combo(op, B, h, 3)
+    for orth in ("mgs", "hybrid"):
+        y, info = krylov.phi_combo(op, B, h, 3, tol=tol, m_max=24, orth=orth)
+        assert info.status == krylov.STATUS_OK
+        assert info.substeps >= 2             # hrho ~ 190: needs substepping
+        assert rel(y, ref) <= 10 * tol
+
+
+def test_zero_step_returns_b0():
+    pr = W.random_problem(43)
+    y, _ = krylov.phi_combo(pr.op, pr.B, 0.0, pr.p, tol=1e-8, m_max=10)
+    assert np.array_equal(y, pr.B[:, 0])
+
+
+def test_zero_operator_gives_taylor_weights():
+    op = W.Operator(kind=W.OP_ADR, nx=6, ny=5)           # nu = a = r = 0
+    rng = np.random.default_rng(44)
+    p, h = 4, 0.7
+    B = rng.standard_normal((op.n, p + 1))
+    ref = sum(h ** k / math.factorial(k) * B[:, k] for k in range(p + 1))
+    y, info = krylov.phi_combo(op, B, h, p, tol=1e-12, m_max=10)
+    assert rel(y, ref) <= 1e-13
+    assert info.breakdowns >= 1
+
+
+def test_p0_is_plain_exponential_and_semigroup():
+    pr = W.random_problem(45, nx=6, ny=5, p=0, h=0.3, with_diag=True)
+    A = operators.dense(pr.op)
+    ref = phi.expm_taylor(pr.h * A) @ pr.B[:, 0]
+    y, _ = krylov.phi_combo(pr.op, pr.B, pr.h, 0, fixed_m=30, fixed_substeps=1, m_max=30)
+    assert rel(y, ref) <= 1e-12
+    y1, _ = krylov.phi_combo(pr.op, pr.B, 0.1, 0, fixed_m=30, fixed_substeps=1, m_max=30)
+    y2, _ = krylov.phi_combo(pr.op, y1[:, None], 0.2, 0, fixed_m=30, fixed_substeps=1,
+                             m_max=30)
+    assert rel(y2, ref) <= 1e-12
+
+
+def test_linearity_in_B_is_exact_for_power_of_two_scaling():
+    pr = W.random_problem(46, nx=12, ny=10, p=2)
+    kw = dict(fixed_m=12, fixed_substeps=2, m_max=12)
+    y1, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, **kw)
+    y2, _ = krylov.phi_combo(pr.op, 4.0 * pr.B, pr.h, pr.p, **kw)
+    assert np.array_equal(y2, 4.0 * y1)
+
+
+def test_balance_scale_does_not_change_result():
+    pr = W.random_problem(47, nx=10, ny=8, p=3)
+    kw = dict(fixed_m=40, fixed_substeps=1, m_max=40)
+    y1, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, **kw)
+    y2, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, mu=1.0, **kw)
+    y3, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, mu=1024.0, **kw)
+    assert rel(y2, y1) <= 1e-12 and rel(y3, y1) <= 1e-12
+    assert krylov.balance_scale(pr.B, pr.p) == 2.0 ** math.floor(
+        math.log2(np.max(np.abs(pr.B[:, 1:]))))
+
+
+def test_nonfinite_input_is_reported():
+    pr = W.random_problem(48)
+    B = pr.B.copy()
+    B[3, 1] = np.nan
+    y, info = krylov.phi_combo(pr.op, B, pr.h, pr.p, tol=1e-8, m_max=10)
+    assert info.status == krylov.STATUS_NONFINITE
+
+
+def test_error_estimate_tracks_true_error():
+    """The (m+1)-st entry of exp(tau Hbar) e_1 estimates the substep error."""
+    pr = W.config1()
+    ref = closed_form.adr_phi_combo(pr.op, pr.B, pr.h, pr.p)
+    for m in (12, 16, 20):
+        y, info = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=m, fixed_substeps=1,
+                                   m_max=m)
+        err = np.linalg.norm(y - ref)
+        assert 0.01 * info.err_max <= err <= 100 * info.err_max
