@@ -1,0 +1,189 @@
+"""Benchmark of the Krylov phi combination on one MI355X.
+
+One timed step = one full phi_combo call (stage, hybrid low-synchronisation
+Arnoldi, small Pade exponential, on-device substep controller, combine) on the
+Allen-Cahn Jacobian workload: A = 0.01 Lap + diag(1 - 3u^2) on a 1024 x 1024
+periodic grid (N = 1,048,576), p = 2, h = 0.1, tol = 1e-8, m <= 64, H-GSMGS.
+The whole call is one cooperative kernel launch.
+
+Printed: one JSON line with Arnoldi steps/s (whole job), phi_combo/s, the
+roofline of the persistent kernel (algorithmic HBM bytes per launch over its
+average duration, HIP events on the launch stream), a fixed-m microbenchmark
+(one substep of exactly 64 Arnoldi steps) with its error against the float64
+CPU oracle, and the oracle's own speed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Arnoldi steps/s and phi_combo/s at N=1M,m=64; HBM GB/s vs peak; err vs FP64"
+
+
+def vectors_per_call(schedule, p, c):
+    """Algorithmic vector passes (each N float64) of one phi_combo call.
+
+    Arnoldi step jj (0-based): matvec+dots reads x_j, p columns of B, c field
+    vectors and jj basis columns, writes w (the first step also writes column
+    0); update reads w and jj+1 columns, writes x_{j+1}:  2 jj + p + c + 5.
+    Combine: m reads + 1 write.  Stage: p+1 reads + 1 write.  The last
+    combine also writes out."""
+    total = (p + 1) + 1
+    for _, m in schedule:
+        total += sum(2 * jj + p + c + 5 for jj in range(m)) + 1 + (m + 1)
+    return total + 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--orth", default="h-gsmgs")
+    ap.add_argument("--basis", default="f64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-m microbenchmark")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    import paper_2410_14917_amd as kp
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    pr = W.config2(side=args.side)
+    N, p = pr.op.n, pr.p
+    c_fields = 1                                   # Allen-Cahn reads u
+    op = kp.Operator.from_host(pr.op, device=dev)
+    B = torch.as_tensor(np.ascontiguousarray(pr.B.T), device=dev)
+    out = torch.empty(N, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # ---- adaptive phi_combo: the timed steps --------------------------------
+    ctx = kp.Context(orth=args.orth, basis=args.basis, stream=stream)
+    info = None
+    for _ in range(args.warmup):
+        _, info = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=pr.m_max, out=out, info=True)
+    sched = ctx.schedule()
+    _, info = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=pr.m_max, out=out, info=True)
+    sched = ctx.schedule()
+    print(f"[bench] adaptive call: {info}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev0[k].record(stream)
+        ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=pr.m_max, out=out)
+        ev1[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
+    avg_ms = float(np.mean(launch_ms))
+    steps_per_call = info["arnoldi_steps"]
+    value = steps_per_call * args.steps / wall
+    vec = vectors_per_call(sched, p, c_fields)
+    bytes_per_call = vec * 8.0 * N
+    achieved = bytes_per_call / (avg_ms * 1e-3) / 1e9
+    print(f"[bench] {args.steps} calls: wall {wall:.3f}s, event avg {avg_ms:.3f} ms/launch, "
+          f"{vec} vector passes/call", file=sys.stderr, flush=True)
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Arnoldi steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.basis == "f64" else "f32-basis/f64",
+        "data": "synthetic",
+        "config": {"workload": f"Allen-Cahn Jacobian 0.01*Lap+diag(1-3u^2), {args.side}x{args.side} "
+                               f"periodic, N={N}, p={p}, h={pr.h}, tol={pr.tol}, m<=64 adaptive, "
+                               f"{args.orth}, one persistent launch per call",
+                   "N": N, "p": p, "m_max": pr.m_max, "tol": pr.tol, "h": pr.h,
+                   "orth": args.orth, "basis": args.basis, "seed": pr.seed},
+        "phi_combo_per_s": round(args.steps / wall, 4),
+        "per_call": {"substeps": info["substeps"], "rejected": info["rejected"],
+                     "arnoldi_steps": steps_per_call, "expm_evals": info["expm_evals"],
+                     "n_fallback": info["n_fallback"], "status": info["status"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "kp::k_persistent<double>",
+                     "bytes_per_launch": bytes_per_call, "avg_launch_ms": round(avg_ms, 4)},
+    }
+
+    # ---- fixed m = 64: one substep, Arnoldi throughput + error vs oracle ------
+    y_fixed = None
+    if not args.no_fixed:
+        fctx = kp.Context(orth=args.orth, basis=args.basis, fixed_m=64, fixed_substeps=1,
+                          stream=stream)
+        for _ in range(max(1, args.warmup)):
+            fctx.phi_combo(op, B, pr.h, m_max=64, out=out)
+        nrep = max(3, args.steps)
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+        torch.cuda.synchronize()
+        for k in range(nrep):
+            e0[k].record(stream)
+            fctx.phi_combo(op, B, pr.h, m_max=64, out=out)
+            e1[k].record(stream)
+        torch.cuda.synchronize()
+        fms = float(np.mean([a.elapsed_time(b) for a, b in zip(e0, e1)]))
+        fvec = vectors_per_call([(pr.h, 64)], p, c_fields)
+        y_fixed = out.cpu().numpy().copy()
+        result["fixed_m64"] = {
+            "ms_per_substep": round(fms, 4),
+            "arnoldi_steps_per_s": round(64 / (fms * 1e-3), 1),
+            "achieved_GBps": round(fvec * 8.0 * N / (fms * 1e-3) / 1e9, 1),
+            "frac": round(fvec * 8.0 * N / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": fvec * 8.0 * N,
+        }
+        fctx.close()
+    ctx.close()
+
+    # ---- CPU oracle baseline (bounded sample) --------------------------------
+    if not args.no_cpu:
+        from oracle import krylov
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = 1
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=64, fixed_substeps=1,
+                                      m_max=64)
+        cw = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": round(64 * reps / cw, 3), "unit": "Arnoldi steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{reps} x one substep of 64 MGS Arnoldi steps + Taylor expm + combine "
+                      f"on the same N={N} workload (numpy float64), {cw:.1f} s"}
+        if y_fixed is not None:
+            err = float(np.linalg.norm(y_fixed - ref) / np.linalg.norm(ref))
+            result["fixed_m64"]["rel_err_vs_oracle"] = err
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * libkrylov_phi: Krylov evaluation of a linear combination of phi-functions
+ * on one MI355X (gfx950).
+ *
+ *     out = sum_{k=0}^{p} h^k phi_k(h A) b_k
+ *
+ * phi_0(z) = e^z, phi_k(z) = int_0^1 e^{(1-s)z} s^{k-1}/(k-1)! ds (arXiv:2410.14917,
+ * Section 2, eq. phi_int_def; the combination is eq. ansatz with the step h of
+ * eq. philincomb).  The combination is the top block of exp(h Atilde) [b_0; e_p]
+ * for the augmented matrix Atilde = [[A, B], [0, K]], B = [b_p, ..., b_1], K the
+ * p x p upper shift (Section 2.1).  That exponential is applied by substepping
+ * (Section 2.2, eq. substep); each substep is a Krylov projection (eq. kryexp)
+ * whose basis comes from the hybrid low-synchronisation Arnoldi process
+ * (Section 3.3, Algorithm 4) with one grid-wide reduction per step and the
+ * correction matrix of Algorithm 5 (H-CWY), 6 (H-NCWY) or 7 (H-GSMGS).
+ *
+ * Conventions
+ *  - All vectors and matrices passed as `const double*` / `double*` are DEVICE
+ *    pointers (hipMalloc'd or equivalent) unless the parameter name ends in
+ *    `_host`.  Device pointers are borrowed: the library never frees them, and
+ *    the caller keeps them alive until the context's stream has passed the call.
+ *  - Matrices are column-major with an explicit leading dimension.
+ *  - Calls enqueue work on the context's stream and return; they are ordered
+ *    with other work on that stream.  A call that fills a `kp_info` or copies
+ *    results to host memory synchronises the stream before it returns.
+ *  - Return codes are synchronous (argument and runtime errors).  Outcomes of
+ *    the computation (not converged, non-finite data) are reported in
+ *    kp_info.status.  No C++ exception crosses this interface.
+ *  - A context is not thread-safe; use one context per stream/thread.
+ */
+#ifndef KRYLOV_PHI_H
+#define KRYLOV_PHI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define KP_OK            0
+#define KP_EINVAL       -1  /* invalid argument (null, out of range, mismatch) */
+#define KP_ENOMEM       -2  /* device allocation failed */
+#define KP_EHIP         -3  /* HIP runtime error (message via kp_last_error) */
+#define KP_EUNSUPPORTED -4  /* combination of options not supported */
+#define KP_ESTATE       -5  /* call out of order (e.g. step before begin) */
+
+/* ---- kp_info.status ------------------------------------------------------ */
+#define KP_STATUS_OK            0
+#define KP_STATUS_NOT_CONVERGED 1  /* max_substeps reached or step size underflow */
+#define KP_STATUS_NONFINITE     2  /* NaN/Inf in the input or the iteration */
+#define KP_STATUS_ABORTED       3  /* a device-wide wait exceeded its limit */
+
+/* ---- orthogonalisation (correction matrix T ~ (V^T V)^{-1}) ------------- */
+#define KP_ORTH_H_GSMGS 0  /* Algorithm 7: T = M^{-1}[I + N M^{-1}], default */
+#define KP_ORTH_H_CWY   1  /* Algorithm 5: T = (I + L)^{-1} by recursion    */
+#define KP_ORTH_H_NCWY  2  /* Algorithm 6: T = I - L (Neumann, two terms)   */
+
+/* ---- operator kinds (matrix-free, 2D periodic, second-order FD) --------- */
+#define KP_OP_ADR         0 /* nu Lap u - ax Dx u - ay Dy u + react u (+ field0 .* u) */
+#define KP_OP_ALLEN_CAHN  1 /* nu Lap u + (1 - 3 field0^2) .* u                       */
+#define KP_OP_BRUSSELATOR 2 /* Jacobian of the 2-species Brusselator at (field0, field1) */
+
+/* ---- basis storage ------------------------------------------------------ */
+#define KP_BASIS_F64 0
+#define KP_BASIS_F32 1   /* basis streamed in FP32; H, T, exp, combination in FP64 */
+
+/* ---- execution ---------------------------------------------------------- */
+#define KP_EXEC_PERSISTENT 0 /* whole call in one cooperative launch (default) */
+#define KP_EXEC_STREAM     1 /* one kernel per phase, fixed schedule only     */
+
+/* Limits. */
+#define KP_MMAX 64   /* largest Krylov dimension m_max */
+#define KP_PMAX 8    /* largest number of phi terms p  */
+
+/*
+ * Operator description, copied at call time.  Grid point (ix, iy) is vector
+ * index iy*nx + ix; neighbours wrap periodically.  Lap = 5-point Laplacian
+ * with spacings dx, dy; Dx, Dy = centred first differences.  For the
+ * Brusselator the state vector is [u-plane; v-plane] (N = 2 nx ny) and the
+ * operator is the Jacobian of
+ *     u' = nu Lap u + brus_a - (brus_b + 1) u + u^2 v,
+ *     v' = nu2 Lap v + brus_b u - u^2 v     at (u, v) = (field0, field1).
+ * transpose != 0 applies A^T instead of A.  field0/field1 are device arrays of
+ * nx*ny doubles (field0 optional for KP_OP_ADR: pass NULL for none).
+ */
+typedef struct kp_op {
+    int32_t kind;
+    int32_t nx, ny;
+    int32_t transpose;
+    double dx, dy;
+    double nu, nu2;
+    double ax, ay;
+    double react;
+    double brus_a, brus_b;
+    const double* field0;
+    const double* field1;
+} kp_op;
+
+/* Context configuration.  Zero-initialise and set what you need; zero fields
+ * take the defaults given. */
+typedef struct kp_config {
+    void*   stream;          /* hipStream_t; NULL = the null stream            */
+    int32_t orth;            /* KP_ORTH_*, default KP_ORTH_H_GSMGS            */
+    int32_t basis_dtype;     /* KP_BASIS_*, default KP_BASIS_F64              */
+    int32_t exec_mode;       /* KP_EXEC_*, default KP_EXEC_PERSISTENT         */
+    int32_t max_substeps;    /* 0 -> 2000                                     */
+    int32_t fixed_m;         /* >0: every substep uses exactly this m          */
+    int32_t fixed_substeps;  /* with fixed_m: number of equal substeps (>=1)   */
+    double  fallback_delta;  /* exact norm replaces the estimate when
+                                ||w||^2 - ss <= delta ||w||^2; 0 -> 1e-10,
+                                negative -> 0 (the printed rule)              */
+    double  breakdown_eps;   /* lucky breakdown when ||v|| <= eps ||A v_j||;
+                                0 -> 1e-12                                     */
+} kp_config;
+
+/* Outcome of a call (filled after the stream is synchronised). */
+typedef struct kp_info {
+    int32_t status;          /* KP_STATUS_* */
+    int32_t substeps;        /* accepted substeps */
+    int32_t rejected;        /* rejected trials (m growth or tau reduction) */
+    int32_t arnoldi_steps;   /* Arnoldi steps = operator applications */
+    int32_t expm_evals;      /* small exponentials evaluated */
+    int32_t m_last;          /* Krylov dimension of the last substep */
+    int32_t n_fallback;      /* steps where the exact norm replaced the estimate */
+    int32_t breakdowns;      /* lucky breakdowns */
+    int32_t schedule_len;    /* entries available through kp_get_schedule */
+    int32_t reserved;
+    double  err_max;         /* largest substep error estimate */
+    double  mu;              /* power-of-two balance of the augmented block */
+    double  t_end;           /* time reached (h on success) */
+} kp_info;
+
+typedef struct kp_ctx kp_ctx;
+
+/* Create a context bound to cfg->stream (cfg may be NULL for defaults).
+ * Allocates nothing on the device until the first call that needs memory.
+ * Errors: KP_EINVAL (out == NULL or an option out of range). */
+int kp_create(kp_ctx** out, const kp_config* cfg);
+
+/* Free the context's device workspace (after synchronising its stream). */
+int kp_destroy(kp_ctx* ctx);
+
+/* Replace the configuration (same validation as kp_create). */
+int kp_set_config(kp_ctx* ctx, const kp_config* cfg);
+
+/*
+ * out[0..N) = sum_{k=0}^{p} h^k phi_k(h A) b_k.
+ *   B    : device, N x (p+1) column-major, leading dimension ldb >= N,
+ *          columns b_0..b_p.  N = nx*ny (x2 for the Brusselator).
+ *   out  : device, N doubles, must not overlap B or the operator fields.
+ *   tol  : relative accuracy target of the adaptive substep controller
+ *          (ignored with a fixed schedule); tol > 0.
+ *   m_max: Krylov dimension cap, 1 <= m_max <= KP_MMAX.
+ *   info : optional; when non-NULL the stream is synchronised and filled.
+ * Asynchronous otherwise.  The context grows its workspace on demand.
+ * Errors: KP_EINVAL, KP_EUNSUPPORTED (adaptive schedule with
+ * KP_EXEC_STREAM), KP_ENOMEM, KP_EHIP.
+ */
+int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
+                 int64_t ldb, double h, double tol, int32_t m_max,
+                 double* out, kp_info* info);
+
+/* Copy the (tau_i, m_i) of the accepted substeps of the last call into host
+ * arrays of capacity cap; returns the number copied (>= 0) or a KP_E code. */
+int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap);
+
+/*
+ * Step-by-step Arnoldi (Algorithm 4) for inspection and tests.
+ * kp_arnoldi_begin stages z = [b_0; mu e_p] for (A, B, p) and resets the
+ * process with capacity m_max; kp_arnoldi_step advances it by nsteps steps
+ * (fewer on lucky breakdown); kp_arnoldi_read synchronises and copies:
+ *   H_host    : (m_max+1) x m_max column-major (may be NULL),
+ *   V_host    : (N+p) x (j+1) column-major unit basis vectors, the last one
+ *               normalised by its exact norm (may be NULL),
+ *   j_host    : number of completed steps, beta_host: ||z||,
+ *   flags_host: [breakdown, n_fallback] (may be NULL).
+ */
+int kp_arnoldi_begin(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
+                     int64_t ldb, int32_t m_max);
+int kp_arnoldi_step(kp_ctx* ctx, int32_t nsteps);
+int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host,
+                    double* beta_host, int32_t* flags_host);
+
+/*
+ * Small phi evaluation on its own, for tests: F = exp(tau * Hbar) e_1 with the
+ * (m+1) x (m+1) matrix Hbar = [[H_m, 0], [h_{m+1,m} e_m^T, 0]] read from the
+ * host array H_host ((m+1) x m column-major, leading dimension ldh >= m+1).
+ * Runs the device's Pade [13/13] scaling-and-squaring routine in one
+ * workgroup and copies F (m+1 doubles) to F_host.
+ */
+int kp_expm_hbar(kp_ctx* ctx, const double* H_host, int32_t ldh, int32_t m,
+                 double tau, double* F_host);
+
+/* Static description of a return code. */
+const char* kp_strerror(int code);
+
+/* Text of the last KP_EHIP error on this context (or "" ). */
+const char* kp_last_error(kp_ctx* ctx);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int kp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRYLOV_PHI_H */

@@ -1,0 +1,184 @@
+"""Krylov evaluation of sum_k h^k phi_k(hA) b_k on an MI355X (gfx950).
+
+Thin PyTorch binding over libkrylov_phi (include/krylov_phi.h): torch supplies
+device memory and the current stream; every step of the computation runs in
+the library's HIP kernels.  See arXiv:2410.14917, Section 3.3 (Algorithm 4)
+for the hybrid low-synchronisation Arnoldi process the library implements.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+from . import _lib
+from ._lib import (KP_OP_ADR, KP_OP_ALLEN_CAHN, KP_OP_BRUSSELATOR, KpConfig, KpInfo,
+                   KpOp)
+
+__all__ = ["Context", "Operator", "phi_combo", "KP_OP_ADR", "KP_OP_ALLEN_CAHN",
+           "KP_OP_BRUSSELATOR"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Operator:
+    """Matrix-free 2D periodic operator on the GPU (fields are device tensors)."""
+
+    def __init__(self, kind, nx, ny, nu=0.0, nu2=0.0, ax=0.0, ay=0.0, react=0.0,
+                 brus_a=1.0, brus_b=3.0, field0=None, field1=None, transpose=False,
+                 dx=None, dy=None):
+        self.kind, self.nx, self.ny = int(kind), int(nx), int(ny)
+        self.nu, self.nu2, self.ax, self.ay = float(nu), float(nu2), float(ax), float(ay)
+        self.react, self.brus_a, self.brus_b = float(react), float(brus_a), float(brus_b)
+        self.dx = float(dx) if dx else 1.0 / nx
+        self.dy = float(dy) if dy else 1.0 / ny
+        self.field0, self.field1 = field0, field1
+        self.transpose = bool(transpose)
+
+    @classmethod
+    def from_host(cls, op, device="cuda"):
+        """From a workloads.Operator (numpy fields) to device tensors."""
+        torch = _torch()
+        f0 = None if op.field0 is None else torch.as_tensor(op.field0, dtype=torch.float64,
+                                                            device=device).contiguous()
+        f1 = None if op.field1 is None else torch.as_tensor(op.field1, dtype=torch.float64,
+                                                            device=device).contiguous()
+        return cls(op.kind, op.nx, op.ny, nu=op.nu, nu2=op.nu2, ax=op.ax, ay=op.ay,
+                   react=op.react, brus_a=op.brus_a, brus_b=op.brus_b, field0=f0,
+                   field1=f1, transpose=op.transpose, dx=op.dx, dy=op.dy)
+
+    @property
+    def n(self):
+        return self.nx * self.ny * (2 if self.kind == KP_OP_BRUSSELATOR else 1)
+
+    def c_struct(self) -> KpOp:
+        def ptr(t):
+            if t is None:
+                return None
+            if t.dtype != _torch().float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("operator fields must be contiguous float64 device tensors")
+            return ctypes.c_void_p(t.data_ptr())
+        return KpOp(self.kind, self.nx, self.ny, int(self.transpose), self.dx, self.dy,
+                    self.nu, self.nu2, self.ax, self.ay, self.react, self.brus_a,
+                    self.brus_b, ptr(self.field0), ptr(self.field1))
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns a kp_ctx (device workspace, configuration, stream)."""
+
+    def __init__(self, orth="h-gsmgs", basis="f64", exec_mode="persistent", max_substeps=0,
+                 fixed_m=0, fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0,
+                 stream=None):
+        self.lib = _lib.load()
+        self._stream = stream
+        self.cfg = KpConfig(_stream_handle(stream), _lib.ORTH[orth], _lib.BASIS[basis],
+                            _lib.EXEC[exec_mode], int(max_substeps), int(fixed_m),
+                            int(fixed_substeps), float(fallback_delta), float(breakdown_eps))
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.kp_create(ctypes.byref(h), ctypes.byref(self.cfg)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.kp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def _check_B(B, n):
+        torch = _torch()
+        if B.dtype != torch.float64 or not B.is_cuda:
+            raise ValueError("B must be a float64 device tensor of shape (p+1, N)")
+        if B.dim() != 2 or B.shape[1] != n or B.stride(1) != 1:
+            raise ValueError(f"B must have shape (p+1, {n}) with unit stride along N")
+        return B.shape[0] - 1, B.stride(0)
+
+    def phi_combo(self, op: Operator, B, h: float, tol: float = 1e-8, m_max: int = 64,
+                  out=None, info: bool = False):
+        """out = sum_k h^k phi_k(h A) b_k; B is (p+1, N), row k = b_k."""
+        torch = _torch()
+        n = op.n
+        p, ldb = self._check_B(B, n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=B.device)
+        opc = op.c_struct()
+        inf = KpInfo() if info else None
+        rc = self.lib.kp_phi_combo(self.h, ctypes.byref(opc), ctypes.c_void_p(B.data_ptr()),
+                                   p, ldb, float(h), float(tol), int(m_max),
+                                   ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.byref(inf) if inf is not None else None)
+        _lib.check(rc, self.h)
+        return (out, inf.as_dict()) if info else out
+
+    def schedule(self, cap: int = 8192):
+        import numpy as np
+        tau = np.zeros(cap)
+        m = np.zeros(cap, dtype=np.int32)
+        n = _lib.check(self.lib.kp_get_schedule(self.h, tau.ctypes.data_as(ctypes.c_void_p),
+                                                m.ctypes.data_as(ctypes.c_void_p), cap), self.h)
+        return list(zip(tau[:n].tolist(), m[:n].tolist()))
+
+    def arnoldi_begin(self, op: Operator, B, m_max: int):
+        p, ldb = self._check_B(B, op.n)
+        self._arn = (op, B, m_max, p)
+        opc = op.c_struct()
+        _lib.check(self.lib.kp_arnoldi_begin(self.h, ctypes.byref(opc),
+                                             ctypes.c_void_p(B.data_ptr()), p, ldb, m_max),
+                   self.h)
+
+    def arnoldi_step(self, nsteps: int = 1):
+        _lib.check(self.lib.kp_arnoldi_step(self.h, int(nsteps)), self.h)
+
+    def arnoldi_read(self, want_basis: bool = True):
+        import numpy as np
+        op, B, m_max, p = self._arn
+        H = np.zeros((m_max + 1) * m_max)
+        j = ctypes.c_int32()
+        beta = ctypes.c_double()
+        flags = (ctypes.c_int32 * 2)()
+        _lib.check(self.lib.kp_arnoldi_read(self.h, H.ctypes.data_as(ctypes.c_void_p), None,
+                                            ctypes.byref(j), ctypes.byref(beta), flags), self.h)
+        V = None
+        if want_basis:
+            V = np.zeros((j.value + 1) * (op.n + p))
+            _lib.check(self.lib.kp_arnoldi_read(self.h, None, V.ctypes.data_as(ctypes.c_void_p),
+                                                None, None, None), self.h)
+            V = V.reshape(j.value + 1, op.n + p).T
+        return {"H": H.reshape(m_max, m_max + 1).T, "j": j.value, "beta": beta.value,
+                "breakdown": flags[0], "n_fallback": flags[1], "V": V}
+
+    def expm_hbar(self, H, m: int, tau: float):
+        """exp(tau Hbar) e_1 by the device's Pade routine; H is (m+1) x m."""
+        import numpy as np
+        Hf = np.asfortranarray(np.asarray(H, dtype=np.float64)[:m + 1, :m])
+        F = np.zeros(m + 1)
+        _lib.check(self.lib.kp_expm_hbar(self.h, Hf.ctypes.data_as(ctypes.c_void_p), m + 1, m,
+                                         float(tau), F.ctypes.data_as(ctypes.c_void_p)), self.h)
+        return F
+
+
+def phi_combo(op: Operator, B, h: float, tol: float = 1e-8, m_max: int = 64,
+              info: bool = False, **ctx_kw):
+    """One-shot convenience wrapper (creates and frees a Context)."""
+    with Context(**ctx_kw) as ctx:
+        return ctx.phi_combo(op, B, h, tol=tol, m_max=m_max, info=info)

@@ -1,0 +1,146 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments before touching the GPU (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_14917_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "krylov_phi.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(kp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_expected_functions():
+    decl = _declared_functions()
+    assert set(decl) == set(_lib.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_constants_match_header():
+    text = open(HEADER).read()
+    for name in ("KP_OK", "KP_EINVAL", "KP_EUNSUPPORTED", "KP_ORTH_H_GSMGS", "KP_ORTH_H_NCWY",
+                 "KP_OP_BRUSSELATOR", "KP_BASIS_F32", "KP_EXEC_STREAM", "KP_MMAX", "KP_PMAX",
+                 "KP_STATUS_NONFINITE"):
+        m = re.search(rf"#define\s+{name}\s+(-?\d+)", text)
+        assert m and int(m.group(1)) == getattr(_lib, name), name
+
+
+def test_struct_layouts_match_header_sizes():
+    assert ctypes.sizeof(_lib.KpOp) == 4 * 4 + 9 * 8 + 2 * 8
+    assert ctypes.sizeof(_lib.KpConfig) == 8 + 6 * 4 + 2 * 8
+    assert ctypes.sizeof(_lib.KpInfo) == 10 * 4 + 3 * 8
+
+
+def test_version_and_strerror():
+    lib = _lib.load()
+    assert lib.kp_version() == 10000
+    assert lib.kp_strerror(-1) == b"invalid argument"
+    assert lib.kp_strerror(12345) == b"unknown error"
+
+
+def _ctx(**kw):
+    lib = _lib.load()
+    cfg = _lib.KpConfig(None, 0, 0, 0, 0, 0, 0, 0.0, 0.0)
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    h = ctypes.c_void_p()
+    rc = lib.kp_create(ctypes.byref(h), ctypes.byref(cfg))
+    return lib, h, rc
+
+
+@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("exec_mode", -1),
+                                       ("fixed_m", 65), ("max_substeps", -2)])
+def test_create_rejects_bad_config(field, val):
+    lib, h, rc = _ctx(**{field: val})
+    assert rc == _lib.KP_EINVAL
+
+
+def test_create_rejects_fixed_m_without_substeps():
+    lib, h, rc = _ctx(fixed_m=10, fixed_substeps=0)
+    assert rc == _lib.KP_EINVAL
+
+
+FAKE = ctypes.c_void_p(0x10000)      # never dereferenced: validation comes first
+FAKE2 = ctypes.c_void_p(0x90000000)
+
+
+def _op(**kw):
+    base = dict(kind=0, nx=8, ny=8, transpose=0, dx=0.125, dy=0.125, nu=0.01, nu2=0.0,
+                ax=1.0, ay=0.5, react=0.0, brus_a=1.0, brus_b=3.0, field0=None, field1=None)
+    base.update(kw)
+    return _lib.KpOp(**base)
+
+
+@pytest.mark.parametrize("opkw,args", [
+    (dict(kind=5), {}),
+    (dict(nx=0), {}),
+    (dict(dx=0.0), {}),
+    (dict(nu=float("nan")), {}),
+    (dict(kind=1), {}),                      # Allen-Cahn needs field0
+    (dict(kind=2, field0=0x20000), {}),      # Brusselator needs both fields
+    ({}, dict(p=-1)),
+    ({}, dict(p=9)),
+    ({}, dict(ldb=63)),
+    ({}, dict(m_max=0)),
+    ({}, dict(m_max=65)),
+    ({}, dict(tol=0.0)),
+    ({}, dict(h=-1.0)),
+    ({}, dict(h=float("inf"))),
+    ({}, dict(out=None)),
+    ({}, dict(out="overlap")),
+])
+def test_phi_combo_rejects_bad_arguments(opkw, args):
+    lib, h, rc = _ctx()
+    assert rc == 0
+    try:
+        op = _op(**opkw)
+        a = dict(B=FAKE, p=2, ldb=64, h=0.1, tol=1e-8, m_max=10, out=FAKE2)
+        a.update(args)
+        if a["out"] == "overlap":
+            a["out"] = ctypes.c_void_p(0x10000 + 8 * 10)
+        rc = lib.kp_phi_combo(h, ctypes.byref(op), a["B"], a["p"], a["ldb"], a["h"], a["tol"],
+                              a["m_max"], a["out"], None)
+        assert rc == _lib.KP_EINVAL
+    finally:
+        lib.kp_destroy(h)
+
+
+def test_stream_mode_needs_fixed_schedule():
+    lib, h, rc = _ctx(exec_mode=1)
+    try:
+        op = _op()
+        rc = lib.kp_phi_combo(h, ctypes.byref(op), FAKE, 2, 64, 0.1, 1e-8, 10, FAKE2, None)
+        assert rc == _lib.KP_EUNSUPPORTED
+    finally:
+        lib.kp_destroy(h)
+
+
+def test_step_before_begin_is_a_state_error():
+    lib, h, rc = _ctx()
+    try:
+        assert lib.kp_arnoldi_step(h, 1) == _lib.KP_ESTATE
+        assert lib.kp_arnoldi_read(h, None, None, None, None, None) == _lib.KP_ESTATE
+    finally:
+        lib.kp_destroy(h)
+
+
+def test_null_context_is_invalid():
+    lib = _lib.load()
+    op = _op()
+    assert lib.kp_phi_combo(None, ctypes.byref(op), FAKE, 2, 64, 0.1, 1e-8, 10, FAKE2, None) \
+        == _lib.KP_EINVAL
+    assert lib.kp_destroy(None) == _lib.KP_EINVAL
+    assert lib.kp_create(None, None) == _lib.KP_EINVAL
