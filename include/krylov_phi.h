@@ -65,10 +65,6 @@ extern "C" {
 #define KP_BASIS_F64 0
 #define KP_BASIS_F32 1   /* basis streamed in FP32; H, T, exp, combination in FP64 */
 
-/* ---- execution ---------------------------------------------------------- */
-#define KP_EXEC_PERSISTENT 0 /* whole call in one cooperative launch (default) */
-#define KP_EXEC_STREAM     1 /* one kernel per phase, fixed schedule only     */
-
 /* Limits. */
 #define KP_MMAX 64   /* largest Krylov dimension m_max */
 #define KP_PMAX 8    /* largest number of phi terms p  */
@@ -103,7 +99,7 @@ typedef struct kp_config {
     void*   stream;          /* hipStream_t; NULL = the null stream            */
     int32_t orth;            /* KP_ORTH_*, default KP_ORTH_H_GSMGS            */
     int32_t basis_dtype;     /* KP_BASIS_*, default KP_BASIS_F64              */
-    int32_t exec_mode;       /* KP_EXEC_*, default KP_EXEC_PERSISTENT         */
+    int32_t reserved0;       /* must be 0                                     */
     int32_t max_substeps;    /* 0 -> 2000                                     */
     int32_t fixed_m;         /* >0: every substep uses exactly this m          */
     int32_t fixed_substeps;  /* with fixed_m: number of equal substeps (>=1)   */
@@ -153,9 +149,11 @@ int kp_set_config(kp_ctx* ctx, const kp_config* cfg);
  *          (ignored with a fixed schedule); tol > 0.
  *   m_max: Krylov dimension cap, 1 <= m_max <= KP_MMAX.
  *   info : optional; when non-NULL the stream is synchronised and filled.
- * Asynchronous otherwise.  The context grows its workspace on demand.
- * Errors: KP_EINVAL, KP_EUNSUPPORTED (adaptive schedule with
- * KP_EXEC_STREAM), KP_ENOMEM, KP_EHIP.
+ * The whole call (staging, every Arnoldi step, small exponentials, substep
+ * control, combination) is ONE cooperative kernel launch on the context's
+ * stream; control never returns to the host in between.  Asynchronous unless
+ * info is requested.  The context grows its workspace on demand.
+ * Errors: KP_EINVAL, KP_ENOMEM, KP_EHIP.
  */
 int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
                  int64_t ldb, double h, double tol, int32_t m_max,
@@ -169,7 +167,8 @@ int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap)
  * Step-by-step Arnoldi (Algorithm 4) for inspection and tests.
  * kp_arnoldi_begin stages z = [b_0; mu e_p] for (A, B, p) and resets the
  * process with capacity m_max; kp_arnoldi_step advances it by nsteps steps
- * (fewer on lucky breakdown); kp_arnoldi_read synchronises and copies:
+ * (fewer on lucky breakdown; each call is one launch of the same persistent
+ * kernel, paused at a step boundary); kp_arnoldi_read synchronises and copies:
  *   H_host    : (m_max+1) x m_max column-major (may be NULL),
  *   V_host    : (N+p) x (j+1) column-major unit basis vectors, the last one
  *               normalised by its exact norm (may be NULL),

@@ -75,13 +75,12 @@ def _stream_handle(stream=None):
 class Context:
     """Owns a kp_ctx (device workspace, configuration, stream)."""
 
-    def __init__(self, orth="h-gsmgs", basis="f64", exec_mode="persistent", max_substeps=0,
-                 fixed_m=0, fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0,
-                 stream=None):
+    def __init__(self, orth="h-gsmgs", basis="f64", max_substeps=0, fixed_m=0,
+                 fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0, stream=None):
         self.lib = _lib.load()
         self._stream = stream
         self.cfg = KpConfig(_stream_handle(stream), _lib.ORTH[orth], _lib.BASIS[basis],
-                            _lib.EXEC[exec_mode], int(max_substeps), int(fixed_m),
+                            0, int(max_substeps), int(fixed_m),
                             int(fixed_substeps), float(fallback_delta), float(breakdown_eps))
         h = ctypes.c_void_p()
         _lib.check(self.lib.kp_create(ctypes.byref(h), ctypes.byref(self.cfg)))

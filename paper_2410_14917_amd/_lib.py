@@ -18,12 +18,10 @@ KP_STATUS_OK, KP_STATUS_NOT_CONVERGED, KP_STATUS_NONFINITE, KP_STATUS_ABORTED = 
 KP_ORTH_H_GSMGS, KP_ORTH_H_CWY, KP_ORTH_H_NCWY = 0, 1, 2
 KP_OP_ADR, KP_OP_ALLEN_CAHN, KP_OP_BRUSSELATOR = 0, 1, 2
 KP_BASIS_F64, KP_BASIS_F32 = 0, 1
-KP_EXEC_PERSISTENT, KP_EXEC_STREAM = 0, 1
 KP_MMAX, KP_PMAX = 64, 8
 
 ORTH = {"h-gsmgs": KP_ORTH_H_GSMGS, "h-cwy": KP_ORTH_H_CWY, "h-ncwy": KP_ORTH_H_NCWY}
 BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
-EXEC = {"persistent": KP_EXEC_PERSISTENT, "stream": KP_EXEC_STREAM}
 
 # Exported symbols (every function declared in the header).
 SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_get_schedule",
@@ -42,7 +40,7 @@ class KpOp(ctypes.Structure):
 
 class KpConfig(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("orth", ctypes.c_int32),
-                ("basis_dtype", ctypes.c_int32), ("exec_mode", ctypes.c_int32),
+                ("basis_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("max_substeps", ctypes.c_int32), ("fixed_m", ctypes.c_int32),
                 ("fixed_substeps", ctypes.c_int32), ("fallback_delta", ctypes.c_double),
                 ("breakdown_eps", ctypes.c_double)]

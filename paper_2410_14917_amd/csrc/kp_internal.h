@@ -1,5 +1,18 @@
-// Internal definitions of libkrylov_phi: device state, kernel arguments,
-// reductions and the grid-wide barrier.  gfx950 (CDNA4), wave64.
+// Internal definitions of libkrylov_phi: layouts, device state, kernel
+// arguments, reductions and the grid-wide barrier.  gfx950 (CDNA4), wave64.
+//
+// Coherence model used throughout.  A workgroup of the persistent kernel stays
+// on one CU for the whole launch, and the L2 caches of the XCDs are not kept
+// coherent with each other inside a kernel: a plain store can sit in the
+// writer's L2 for the rest of the launch.  Therefore no plain-stored data ever
+// crosses workgroups inside a launch.  Each workgroup owns a range of grid
+// rows (in every species plane) and reads/writes only its own elements with
+// plain accesses; everything another workgroup needs -- the first and last row
+// of the range (stencil halo), the augmented tail, partial sums and the
+// published control block -- goes through agent-scope atomic stores and loads
+// (cstore / cload), which write through to and read from the coherent level.
+// The barrier itself is a pair of monotone counters updated with relaxed
+// agent-scope atomics; no cache-wide fence is executed inside the hot loop.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,7 +22,7 @@
 
 namespace kp {
 
-constexpr int kThreads = 1024;            // threads per workgroup, every kernel
+constexpr int kThreads = 512;             // threads per workgroup (one per CU)
 constexpr int kWaves = kThreads / 64;
 constexpr int kMMax = KP_MMAX;
 constexpr int kPMax = KP_PMAX;
@@ -17,47 +30,55 @@ constexpr int kKStride = 2 * kMMax + 8;   // partial-sum slots per workgroup
 constexpr int kLdh = kMMax + 1;           // leading dimension of H in the state
 constexpr int kLdt = kMMax;               // leading dimension of L, M^{-1}
 constexpr int kLogMax = 8192;             // logged substeps
-constexpr int kNm = kMMax + 1;            // largest small-exponential size
-constexpr int kNmPad = 68;                // padded to a multiple of 4
+constexpr int kNmPad = 68;                // small-exponential matrices, padded
 constexpr int kExSlots = 6;               // scratch matrices of the small exp
+constexpr int kTailPad = 64;              // augmented tail region (>= KP_PMAX)
+constexpr int kPlaneAlign = 128;          // plane offset alignment (elements)
 
-// Phases of one phi_combo call (uniform across the grid).
+// Phases of one call (uniform across the grid).
 enum Phase : int {
   PH_STAGE = 0,
-  PH_STEP = 1,
-  PH_EXPM = 2,
-  PH_COMBINE = 3,
-  PH_FINISH = 4,
-  PH_DONE = 5,
+  PH_STEP = 1,     // [pending update] + matvec + grouped dots + scalar step
+  PH_CLOSE = 2,    // pending update + exact norm of the newest vector
+  PH_EXPM = 3,
+  PH_COMBINE = 4,
+  PH_FINISH = 5,
+  PH_DONE = 6,
 };
 
-// State of the call in device memory.  Written only by the leader workgroup
-// of a phase (the last workgroup to arrive at a reduction, or workgroup 0 for
-// the small exponential); read by every workgroup after a grid-wide sync.
-struct State {
+constexpr int kFlagStride = 16;           // unsigned per workgroup flag (64 B)
+
+// Control block published by workgroup 0 after every grid-wide sync and read
+// by every workgroup with coherent loads.
+struct Pub {
   int phase;
-  int sub;            // within PH_STEP: 0 = matvec+dots due, 1 = update due
+  int j;            // completed Arnoldi steps of the current substep
+  int upd;          // the update producing x_j is still pending (PH_STEP/CLOSE)
+  int m_eff;        // Krylov dimension available (combine uses it)
+  int last;         // the accepted substep ends at h
   int status;
-  int j;              // completed Arnoldi steps of the current substep
+  int pad_[2];
+  double inv_mu;
+  double coef[kMMax + 2];   // coefficients of the pending update / of the combine
+};
+
+// Private state of the call, read and written only by workgroup 0 (and by
+// the host between launches).
+struct State {
   int m_target;       // steps to reach before the small exponential
   int m_cur;          // current Krylov dimension choice of the controller
-  int m_eff;          // Krylov dimension available (j, or breakdown size)
   int breakdown;      // lucky breakdown in this substep
-  int fallback_cur;   // the exact norm replaces the estimate at step j
-  int last_substep;   // the accepted substep ends at h
+  int fallback_cur;   // the exact norm replaced the estimate at the last step
   int substeps, rejected, arnoldi_steps, expm_evals, n_fallback, breakdowns;
   int nlog;
   int zero;           // the start vector is zero
-  int aborted;
   int m_last;
-  int pad_[2];
-  double t, tau, beta, mu, inv_mu, err_max, omega, err, last_nrm2;
+  int pad_[3];
+  double t, tau, beta, mu, err_max, omega, err, last_nrm2;
   double sigma[kMMax + 2];   // unit scale of stored basis column i
   double gamma[kMMax + 2];   // divisor applied to column i+1 when it was written
   double wn2[kMMax + 2];     // ||A u_j||^2 of step j
-  double coef[kMMax + 2];    // coefficients of the update / combination pass
   double F[kNmPad];          // exp(tau Hbar) e_1
-  double tv[kKStride];       // reduced inner products of the current step
   double H[kLdh * kMMax];    // Hessenberg, column-major
   double Lm[kLdt * kMMax];   // L (strictly lower), column-major
   double Minv[kLdt * kMMax]; // (I + L)^{-1}, column-major
@@ -65,40 +86,76 @@ struct State {
   int log_m[kLogMax];
 };
 
-// Arguments of every kernel (passed by value).
+// Arguments of the kernels (passed by value).
+//
+// Internal vector layout (length ld): plane s (s < nplanes) at s*npt_pad,
+// row-major nx x ny inside the plane; the augmented tail (p entries) at
+// tail_off; zero padding elsewhere.  The caller's B, fields and out use the
+// plain layout (plane s at s*npt).
 struct Args {
   void* V;            // basis, ld x (m_max + 2), element type per basis_f32
-  double* u;          // substep state vector (length ld), float64
-  const double* B;    // N x (p+1), column-major
+  double* u;          // substep state vector, float64, length ld
+  const double* B;    // caller layout, N x (p+1), column-major
   int64_t ldb;
   const double* f0;
   const double* f1;
   double* out;
-  double* part;       // [nwg][kKStride] partial sums
-  unsigned* sync;     // [0] arrivals, [1] generation, [2] abort
-  State* st;
-  double* ex;         // small-exponential scratch, kExSlots * kNmPad^2
-  int64_t ld;         // leading dimension of V and u
-  int N, L, p, npt, nx, ny;
-  int nwg;
-  int64_t ppw;        // element pairs per workgroup
-  int64_t npairs;
+  double* part;       // [nwg][kKStride] partial sums        (coherent)
+  unsigned* sync;     // [0] arrivals, [1] releases, [2] abort (coherent)
+  State* st;          // workgroup 0 only
+  Pub* pub;           // coherent
+  double* ex;         // small-exponential scratch (workgroup 0)
+  double* hx;         // halo rows [nwg][nplanes][2][nx]      (coherent)
+  double* tx;         // tail values [kTailPad]               (coherent)
+  unsigned* flags;    // per-workgroup production counters, kFlagStride apart
+  int64_t ld, npt_pad, tail_off;
+  int N, p, npt, nx, ny, nplanes;
+  int nwg, rows_per_wg;
   int kind, transpose;
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
   int orth, fixed_m, fixed_substeps, max_substeps, m_max;
-  int persistent;
+  int stop_j;         // pause when this many steps are completed (INT_MAX: never)
   int basis_f32;
-  int pad_;
+  int halo_lds;       // the stencil halo rows fit the LDS copy of the matvec
+  double inv_nx;      // 1 / nx (row of an in-plane index, corrected exactly)
   double h, tol, delta, eps_bd;
-  int64_t wait_ticks;  // bound of a grid-wide wait, steady-counter ticks
+  int64_t wait_ticks; // bound of a grid-wide wait, steady-counter ticks
 };
+
+// ---- coherent (agent-scope) accesses ---------------------------------------
+
+template <typename T>
+__device__ inline T cload(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void cstore(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---- reductions ------------------------------------------------------------
 
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes of a wave, result in every lane.  Rows of 16 lanes are
+// reduced with DPP (quad permutations, half-row and row mirrors); the four row
+// sums are combined through readlane, in a fixed order.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 __device__ inline double wave_max(double v) {
@@ -118,6 +175,7 @@ __device__ inline double block_sum(double v, double* red) {
   double s = 0.0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s += red[w];
+  __syncthreads();
   return s;
 }
 
@@ -130,82 +188,82 @@ __device__ inline double block_max(double v, double* red) {
   double s = red[0];
 #pragma unroll
   for (int w = 1; w < kWaves; ++w) s = fmax(s, red[w]);
+  __syncthreads();
   return s;
 }
 
-// ---- grid synchronisation --------------------------------------------------
+// ---- grid-wide synchronisation ---------------------------------------------
 //
-// Arrival at a grid-wide point.  Every workgroup has already written its
-// partial results.  Thread 0 publishes them (release at agent scope) and takes
-// a ticket; the workgroup holding the last ticket becomes the leader, sees all
-// partials (acquire) and does the reduction and the serial work of the phase.
-// In a persistent launch the other workgroups then wait for the leader's
-// release; in per-phase kernels the kernel boundary is the release.
+// Barrier number k (counted identically by every workgroup): every workgroup
+// increments the arrival counter; workgroup 0 waits until it reads k * nwg,
+// does the serial work of the phase, publishes, and sets the release counter
+// to k; the others wait until they read k.  Each wait is bounded by
+// a.wait_ticks of the steady counter: past it the abort flag is raised and all
+// workgroups leave their main loop at the next check, so a launch always ends.
 
-__device__ inline unsigned atomic_load_acq(unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ inline void wait_all_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Returns true in every thread of the leader workgroup.
-__device__ inline bool arrive(const Args& a, unsigned* gen0_out) {
-  __shared__ int s_last;
-  __shared__ unsigned s_gen;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned g = atomic_load_acq(a.sync + 1);
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(a.sync, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    int last = (prev == (unsigned)(a.nwg - 1));
-    if (last) __threadfence();
-    s_last = last;
-    s_gen = g;
-  }
-  __syncthreads();
-  *gen0_out = s_gen;
-  return s_last != 0;
-}
-
-// Called by the leader after its serial work: reset the ticket counter and
-// (persistent launches) open the barrier.
-__device__ inline void leader_release(const Args& a, unsigned gen0) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(a.sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    __hip_atomic_store(a.sync + 1, gen0 + 1u, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-}
-
-// Non-leaders of a persistent launch wait here.  The wait is bounded: after
-// a.wait_ticks of the steady counter (a few seconds) without the generation
-// moving, the abort flag is raised and every workgroup leaves its main loop at
-// the next check.
-__device__ inline void wait_release(const Args& a, unsigned gen0) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t t0 = wall_clock64();
-    while (atomic_load_acq(a.sync + 1) == gen0) {
-      if (atomic_load_acq(a.sync + 2) != 0u) break;
-      __builtin_amdgcn_s_sleep(2);
+__device__ inline bool spin_until(const Args& a, const unsigned* ctr, unsigned target) {
+  if (cload(ctr) >= target) return true;
+  const int64_t t0 = wall_clock64();
+  for (unsigned it = 1;; ++it) {
+    if (cload(ctr) >= target) return true;
+    if ((it & 31u) == 0u) {
+      if (cload(a.sync + 2) != 0u) return false;
       if (wall_clock64() - t0 > a.wait_ticks) {
-        __hip_atomic_store(a.sync + 2, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        break;
+        cstore(a.sync + 2, 1u);
+        return false;
       }
     }
-    __threadfence();
   }
+}
+
+__device__ inline void bar_arrive(const Args& a) {
+  wait_all_stores();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(a.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroup 0: wait for every arrival at barrier k.
+__device__ inline void bar_gather(const Args& a, unsigned k) {
+  if (threadIdx.x == 0) spin_until(a, a.sync, k * (unsigned)a.nwg);
   __syncthreads();
 }
 
-__device__ inline bool aborted(const Args& a) {
-  __shared__ int s_ab;
+// Workgroup 0: open barrier k after its coherent stores completed.
+__device__ inline void bar_release(const Args& a, unsigned k) {
+  wait_all_stores();
   __syncthreads();
-  if (threadIdx.x == 0) s_ab = (atomic_load_acq(a.sync + 2) != 0u);
+  if (threadIdx.x == 0) cstore(a.sync + 1, k);
+}
+
+// Other workgroups: wait for the release of barrier k.
+__device__ inline void bar_wait(const Args& a, unsigned k) {
+  if (threadIdx.x == 0) spin_until(a, a.sync + 1, k);
   __syncthreads();
-  return s_ab != 0;
+}
+
+// Point-to-point: this workgroup has published the halo rows / tail of the
+// vector it produced in the phase of barrier k.
+__device__ inline void flag_publish(const Args& a, unsigned k) {
+  wait_all_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) cstore(a.flags + (int64_t)blockIdx.x * kFlagStride, k);
+}
+
+// Wait until the two row neighbours (halo) and workgroup 0 (tail) have
+// published the vector of barrier k.
+__device__ inline void flag_wait_neighbours(const Args& a, unsigned k) {
+  if (threadIdx.x == 0) {
+    const int b = (int)blockIdx.x, nw = a.nwg;
+    const int prev = (b == 0) ? nw - 1 : b - 1;
+    const int next = (b + 1 == nw) ? 0 : b + 1;
+    spin_until(a, a.flags + (int64_t)prev * kFlagStride, k);
+    spin_until(a, a.flags + (int64_t)next * kFlagStride, k);
+    spin_until(a, a.flags, k);
+  }
+  __syncthreads();
 }
 
 }  // namespace kp

@@ -1,8 +1,9 @@
-// Serial work of the grid-wide synchronisation points, done by one workgroup
+// Serial work at the grid-wide synchronisation points, done by workgroup 0
 // (the leader) on O(m^2) data: reduction of the per-workgroup partials, the
 // scalar step of the hybrid Arnoldi process, the norm epilogue of the update,
 // the small exponential with the substep controller, and the bookkeeping of
-// the combine.
+// the combine.  The leader owns the State (plain accesses) and publishes what
+// the other workgroups need in the Pub block (coherent stores).
 #pragma once
 
 #include "kp_expm.h"
@@ -10,76 +11,152 @@
 
 namespace kp {
 
-// dst[k] = sum over workgroups of a.part[w][k], k < nslot; fixed order.
-// grp: LDS scratch of 8 * kKStride doubles.
-__device__ inline void reduce_partials(const Args& a, int nslot, double* dst,
-                                       double* grp) {
-  const int g = threadIdx.x >> 7, l = threadIdx.x & 127;   // 8 groups x 128
-  for (int kb = 0; kb < nslot; kb += 128) {
+// dst[k] = sum over workgroups of part[w][k], k < nslot; fixed order.
+// Thread (g, l) of kRg groups sums slot l over the workgroups w = g (mod kRg);
+// its coherent loads are all issued before they are consumed, so the
+// reduction costs about one memory latency per 64 workgroups.
+// grp: LDS scratch of kRg * kKStride doubles.
+constexpr int kRg = 4;
+__device__ inline void reduce_partials(const Args& a, int nslot, double* dst, double* grp) {
+  constexpr int kS = kThreads / kRg;
+  const int g = threadIdx.x / kS, l = threadIdx.x % kS;
+  for (int kb = 0; kb < nslot; kb += kS) {
     const int k = kb + l;
     if (k < nslot) {
       double s = 0.0;
-      for (int w = g; w < a.nwg; w += 8) s += a.part[(int64_t)w * kKStride + k];
+      for (int w0 = 0; w0 < a.nwg; w0 += 64 * kRg) {
+        double v[64];
+#pragma unroll
+        for (int q = 0; q < 64; ++q) {
+          const int w = w0 + g + kRg * q;
+          v[q] = (w < a.nwg) ? cload(a.part + (int64_t)w * kKStride + k) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 64; ++q) s += v[q];
+      }
       grp[g * kKStride + k] = s;
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nslot; k += kThreads) {
     double s = 0.0;
-    for (int gg = 0; gg < 8; ++gg) s += grp[gg * kKStride + k];
+#pragma unroll
+    for (int gg = 0; gg < kRg; ++gg) s += grp[gg * kKStride + k];
     dst[k] = s;
   }
   __syncthreads();
 }
 
-__device__ inline void reduce_max2(const Args& a, double* mx, double* bad) {
-  __shared__ double s_red[kWaves];
+// ---- stage leader: balance mu, augmented tail, first phase -----------------
+__device__ inline void leader_stage(const Args& a, double* red) {
   double m0 = 0.0, m1 = 0.0;
   for (int w = threadIdx.x; w < a.nwg; w += kThreads) {
-    m0 = fmax(m0, a.part[(int64_t)w * kKStride + 0]);
-    m1 = fmax(m1, a.part[(int64_t)w * kKStride + 1]);
+    m0 = fmax(m0, cload(a.part + (int64_t)w * kKStride + 0));
+    m1 = fmax(m1, cload(a.part + (int64_t)w * kKStride + 1));
   }
-  *mx = block_max(m0, s_red);
-  *bad = block_max(m1, s_red);
-}
-
-// ---- stage leader: balance mu, augmented tail, first phase -----------------
-__device__ inline void leader_stage(const Args& a) {
-  double mx, bad;
-  reduce_max2(a, &mx, &bad);
+  const double mx = block_max(m0, red);
+  const double bad = block_max(m1, red);
+  double mu = 1.0;
+  if (a.p > 0 && mx > 0.0 && isfinite(mx)) {
+    int e;
+    frexp(mx, &e);
+    mu = ldexp(1.0, e - 1);            // largest power of two <= max |b_k|
+  }
+  for (int k = threadIdx.x; k < kTailPad; k += kThreads) {
+    const double v = (a.p > 0 && k == a.p - 1) ? mu : 0.0;
+    a.u[a.tail_off + k] = v;
+    cstore(a.tx + k, v);
+  }
   if (threadIdx.x == 0) {
     State* st = a.st;
-    double mu = 1.0;
-    if (a.p > 0 && mx > 0.0 && isfinite(mx)) {
-      int e;
-      frexp(mx, &e);
-      mu = ldexp(1.0, e - 1);          // largest power of two <= max |b_k|
-    }
+    Pub* pb = a.pub;
     st->mu = mu;
-    st->inv_mu = 1.0 / mu;
-    if (a.p > 0) a.u[a.N + a.p - 1] = mu;
+    cstore(&pb->inv_mu, 1.0 / mu);
     if (bad != 0.0) {
-      st->status = KP_STATUS_NONFINITE;
-      st->phase = PH_FINISH;
+      cstore(&pb->status, (int)KP_STATUS_NONFINITE);
+      cstore(&pb->phase, (int)PH_FINISH);
     } else if (a.h == 0.0) {
-      st->phase = PH_FINISH;
+      cstore(&pb->phase, (int)PH_FINISH);
     } else {
-      st->phase = PH_STEP;
-      st->sub = 0;
-      st->j = 0;
+      cstore(&pb->j, 0);
+      cstore(&pb->upd, 0);
+      cstore(&pb->phase, (int)PH_STEP);
     }
   }
 }
 
-// ---- scalar step of Algorithm 4 (one wave) ---------------------------------
+// ---- scalar step of Algorithm 4 --------------------------------------------
+// The leader keeps the correction matrices in LDS for the whole launch
+// (loaded once by load_tables, extended by one row per step, and mirrored in
+// the State for the host and for later launches).  Element (row r, column k)
+// of M^{-1} = (I + L)^{-1} / of L is at Mi[k * kTabLd + r] / Li[k * kTabLd + r];
+// sg[i] = sigma_i.
+constexpr int kTabLd = kMMax + 1;
+constexpr int kTabDoubles = 2 * kMMax * kTabLd + kMMax + 8;
+
+__device__ inline void load_tables(const Args& a, double* tabs) {
+  const State* st = a.st;
+  double* Mi = tabs;
+  double* Li = tabs + kMMax * kTabLd;
+  double* sg = tabs + 2 * kMMax * kTabLd;
+  for (int idx = threadIdx.x; idx < kMMax * kMMax; idx += kThreads) {
+    const int k = idx / kMMax, r = idx - k * kMMax;
+    Mi[k * kTabLd + r] = st->Minv[(int64_t)k * kLdt + r];
+    Li[k * kTabLd + r] = st->Lm[(int64_t)k * kLdt + r];
+  }
+  for (int i = threadIdx.x; i < kMMax; i += kThreads) sg[i] = st->sigma[i];
+  __syncthreads();
+}
+
+// Work arrays of the scalar step in LDS (doubles).
+constexpr int kWkL = 0, kWkB = 72, kWkY = 144, kWkP = 216, kWkPart = 288;
+constexpr int kWkDoubles = kWkPart + kWaves * 64;
+
+// dst[i] = sum over k in K(i) of T(i, k) * v[k] for rows i <= jj, where the
+// k range is split over the kWaves waves (wave g takes k = g, g + kWaves, ...)
+// and the partial sums meet in LDS.  T(i, k) = tab[k * kTabLd + i] (TR = false)
+// or tab[i * kTabLd + k] (TR = true, the transposed table).  MODE selects
+// K(i): 0 -> k <= i, 1 -> k < i, 2 -> i < k <= jj.
+template <int MODE, bool TR>
+__device__ inline double tri_mv(int jj, const double* tab, const double* v, double* part) {
+  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (i <= jj) {
+    const int klo = (MODE == 2) ? i + 1 : 0;
+    const int khi = (MODE == 0) ? i : (MODE == 1 ? i - 1 : jj);
+    for (int k = g; k <= khi; k += kWaves)
+      if (k >= klo) acc += (TR ? tab[i * kTabLd + k] : tab[k * kTabLd + i]) * v[k];
+  }
+  part[g * 64 + i] = acc;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += part[w * 64 + i];
+  }
+  __syncthreads();
+  return s;   // meaningful in wave 0
+}
+
 // tv: reduced inner products of step jj (slot layout of matvec_dots_pass).
 // Stored columns x_i carry unit scales sigma_i (u_i = sigma_i x_i); x_j is the
 // vector the matvec multiplied, so alpha = ||x_j|| is the lagged true norm and
 // H_{j,j-1} = gamma_{j-1} alpha (gamma = divisor applied to x_j when written).
-__device__ inline void scalar_step(const Args& a, int jj, const double* tv) {
-  if (threadIdx.x >= 64) return;
+// Every thread of the workgroup calls this; wave 0 holds row i = lane.
+__device__ inline void scalar_step(const Args& a, int jj, const double* tv, double* tabs,
+                                   double* wk) {
   State* st = a.st;
-  const int i = threadIdx.x;               // lane = row index
+  Pub* pb = a.pub;
+  double* Mi = tabs;
+  double* Li = tabs + kMMax * kTabLd;
+  double* sg = tabs + 2 * kMMax * kTabLd;
+  double* sl = wk + kWkL;
+  double* sb = wk + kWkB;
+  double* sy = wk + kWkY;
+  double* sp = wk + kWkP;
+  double* part = wk + kWkPart;
+  const int i = threadIdx.x;               // row index in wave 0
+  const bool w0 = threadIdx.x < 64;
   const double gj = tv[2 * jj], cj = tv[2 * jj + 1], cww = tv[2 * jj + 2];
   const double alpha = sqrt(gj);
   if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(cww)) {
@@ -87,92 +164,99 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv) {
       if (jj == 0 && alpha == 0.0) {        // zero start vector: result is zero
         st->zero = 1;
         st->beta = 0.0;
-        st->phase = PH_FINISH;
+        cstore(&pb->phase, (int)PH_FINISH);
       } else if (alpha == 0.0) {            // exact invariance already reached
         st->breakdown = 1;
-        st->m_eff = jj;
+        cstore(&pb->m_eff, jj);
+        cstore(&pb->upd, 0);
         st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
-        st->phase = PH_EXPM;
+        cstore(&pb->phase, (int)PH_EXPM);
       } else {
-        st->status = KP_STATUS_NONFINITE;
-        st->phase = PH_FINISH;
+        cstore(&pb->status, (int)KP_STATUS_NONFINITE);
+        cstore(&pb->phase, (int)PH_FINISH);
       }
     }
     return;
   }
+  if (jj > 0 && st->fallback_cur && alpha <= a.eps_bd * sqrt(st->wn2[jj - 1])) {
+    // the exact norm of the vector produced with the fallback is negligible:
+    // lucky breakdown at the previous step (this step's products are unused)
+    if (i == 0) {
+      st->breakdown = 1;
+      st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
+      cstore(&pb->j, jj);
+      cstore(&pb->m_eff, jj);
+      cstore(&pb->upd, 0);
+      cstore(&pb->phase, (int)PH_EXPM);
+    }
+    return;
+  }
   const double sj = 1.0 / alpha;
-  const bool act = i < jj;
-  const double sig = act ? st->sigma[i] : (i == jj ? sj : 0.0);
+  const bool act = w0 && i < jj;
+  const double sig = act ? sg[i] : (i == jj ? sj : 0.0);
   const double l = act ? sig * tv[2 * i] * sj : 0.0;                 // L_{j,i}
   const double b = act ? sig * tv[2 * i + 1] * sj : (i == jj ? cj * sj * sj : 0.0);
   const double wn2 = cww * sj * sj;
-  // new row of M^{-1} = (I + L)^{-1} by the compact-WY recursion
-  double mr = (i == jj) ? 1.0 : 0.0;
-  for (int k = 0; k < jj; ++k) {
-    const double lk = __shfl(l, k, 64);
-    if (act && i <= k) mr -= lk * st->Minv[(int64_t)i * kLdt + k];
+  if (w0) {
+    sl[i] = l;
+    sb[i] = b;
   }
+  __syncthreads();
+  // new row of M^{-1} = (I + L)^{-1} by the compact-WY recursion:
+  // (M^{-1})_{j,i} = -sum_{i <= k < j} L_{j,k} (M^{-1})_{k,i}; the row is
+  // appended to the LDS tables together with the new row of L.
+  const double mr = -tri_mv<2, true>(jj - 1, Mi, sl, part);   // k in (i, jj-1] ...
+  // (tri_mv<2> excludes k == i; add the unit-diagonal term L_{j,i} * 1)
+  if (act) {
+    Mi[i * kTabLd + jj] = mr - l;
+    Li[i * kTabLd + jj] = l;
+  }
+  if (i == 0) {
+    Mi[jj * kTabLd + jj] = 1.0;
+    Li[jj * kTabLd + jj] = 0.0;
+  }
+  __syncthreads();
   double Hi = 0.0;
   if (a.orth == KP_ORTH_H_NCWY) {
     // T = I - L:  H = b - L b
-    double s = 0.0;
-    for (int k = 0; k < jj; ++k) {
-      const double bk = __shfl(b, k, 64);
-      if (act && k < i) s += st->Lm[(int64_t)k * kLdt + i] * bk;
-    }
-    const double hj = b - wave_sum((i < jj) ? l * b : 0.0);
-    Hi = act ? b - s : (i == jj ? hj : 0.0);
+    Hi = b - tri_mv<1, false>(jj, Li, sb, part);
   } else {
     // y = M^{-1} b  (CWY: H = y)
-    double y = 0.0;
-    for (int k = 0; k < jj; ++k) {
-      const double bk = __shfl(b, k, 64);
-      if (act && k <= i) y += st->Minv[(int64_t)k * kLdt + i] * bk;
-    }
-    const double yj = wave_sum((i <= jj) ? mr * b : 0.0);
-    if (i == jj) y = yj;
+    const double y = tri_mv<0, false>(jj, Mi, sb, part);
     if (a.orth == KP_ORTH_H_CWY) {
-      Hi = (i <= jj) ? y : 0.0;
+      Hi = y;
     } else {
-      // GSMGS: p = b + N y = b - L^T y, then forward substitution (I + L) x = p
-      double pv = b;
-      for (int k = 0; k <= jj; ++k) {
-        const double yk = __shfl(y, k, 64);
-        if (i < k) {
-          const double Lki = (k < jj) ? st->Lm[(int64_t)i * kLdt + k] : l;
-          pv -= Lki * yk;
-        }
-      }
-      double x = pv;
-      for (int k = 0; k < jj; ++k) {
-        const double xk = __shfl(x, k, 64);
-        const double lk = __shfl(l, k, 64);
-        if (i > k && i <= jj) {
-          const double Lik = (i < jj) ? st->Lm[(int64_t)k * kLdt + i] : lk;
-          x -= Lik * xk;
-        }
-      }
-      Hi = (i <= jj) ? x : 0.0;
+      // GSMGS: p = b + N y = b - L^T y, then x = M^{-1} p with the explicit
+      // inverse kept above (the same x as the forward substitution M x = p)
+      if (w0) sy[i] = y;
+      __syncthreads();
+      const double pv = b - tri_mv<2, true>(jj, Li, sy, part);
+      if (w0) sp[i] = pv;
+      __syncthreads();
+      Hi = tri_mv<0, false>(jj, Mi, sp, part);
     }
   }
+  if (!w0) return;
+  if (i > jj) Hi = 0.0;
   const double ss = wave_sum((i <= jj) ? b * b : 0.0);
   const double est2 = wn2 - ss;
   const int fallback = (est2 <= a.delta * wn2) ? 1 : 0;
   const double gam = fallback ? 1.0 : sqrt(est2);
   const int bd = (!fallback && gam <= a.eps_bd * sqrt(wn2)) ? 1 : 0;
-  const bool bad = !isfinite(wave_sum((i <= jj) ? Hi : 0.0));
-  // write back: correction-matrix rows, H column, coefficients
+  const bool bad = !isfinite(wave_sum(Hi));
+  // write back: correction-matrix rows, H column, update coefficients
   if (act) {
     st->Lm[(int64_t)i * kLdt + jj] = l;
-    st->Minv[(int64_t)i * kLdt + jj] = mr;
+    st->Minv[(int64_t)i * kLdt + jj] = Mi[i * kTabLd + jj];
   }
   if (i <= jj) {
     st->H[(int64_t)jj * kLdh + i] = Hi;
-    st->coef[i] = -Hi * sig / gam;
+    cstore(&pb->coef[i], -Hi * sig / gam);
   }
   if (i == 0) {
+    sg[jj] = sj;
     st->Minv[(int64_t)jj * kLdt + jj] = 1.0;
-    st->coef[jj + 1] = sj / gam;
+    cstore(&pb->coef[jj + 1], sj / gam);
     st->sigma[jj] = sj;
     st->gamma[jj] = gam;
     st->wn2[jj] = wn2;
@@ -181,44 +265,50 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv) {
     st->fallback_cur = fallback;
     st->n_fallback += fallback;
     if (bad) {
-      st->status = KP_STATUS_NONFINITE;
-      st->phase = PH_FINISH;
+      cstore(&pb->status, (int)KP_STATUS_NONFINITE);
+      cstore(&pb->phase, (int)PH_FINISH);
     } else if (bd) {
       st->H[(int64_t)jj * kLdh + jj + 1] = 0.0;
       st->breakdown = 1;
-      st->j = jj + 1;
-      st->m_eff = jj + 1;
       st->arnoldi_steps += 1;
-      st->phase = PH_EXPM;
+      cstore(&pb->j, jj + 1);
+      cstore(&pb->m_eff, jj + 1);
+      cstore(&pb->upd, 0);
+      cstore(&pb->phase, (int)PH_EXPM);
     } else {
-      st->sub = 1;
+      const int j = jj + 1;
+      st->arnoldi_steps += 1;
+      cstore(&pb->j, j);
+      cstore(&pb->m_eff, j);
+      cstore(&pb->upd, 1);
+      cstore(&pb->phase, (int)((j >= st->m_target || j >= a.stop_j) ? PH_CLOSE : PH_STEP));
     }
   }
 }
 
-// ---- after the update pass: exact norm of x_{j+1} --------------------------
-__device__ inline void leader_norm(const Args& a, int jj, double nrm2) {
+// ---- close of the Arnoldi process: exact norm of the newest vector ---------
+// After the pending update produced x_j (j = completed steps), its exact norm
+// gives the last subdiagonal H_{j+1,j} = gamma_{j-1} ||x_j|| (the final
+// reduction of Algorithm 4).
+__device__ inline void leader_close(const Args& a, double nrm2) {
   if (threadIdx.x != 0) return;
   State* st = a.st;
+  Pub* pb = a.pub;
+  const int j = cload(&pb->j);
   const double nrm = sqrt(nrm2);
-  st->H[(int64_t)jj * kLdh + jj + 1] = st->gamma[jj] * nrm;
-  st->arnoldi_steps += 1;
-  st->j = jj + 1;
-  st->m_eff = jj + 1;
-  st->sub = 0;
+  st->H[(int64_t)(j - 1) * kLdh + j] = st->gamma[j - 1] * nrm;
   st->last_nrm2 = nrm2;
+  cstore(&pb->upd, 0);
   if (!isfinite(nrm2)) {
-    st->status = KP_STATUS_NONFINITE;
-    st->phase = PH_FINISH;
+    cstore(&pb->status, (int)KP_STATUS_NONFINITE);
+    cstore(&pb->phase, (int)PH_FINISH);
     return;
   }
-  if (st->fallback_cur && nrm <= a.eps_bd * sqrt(st->wn2[jj])) {
-    st->H[(int64_t)jj * kLdh + jj + 1] = 0.0;
+  if (st->fallback_cur && nrm <= a.eps_bd * sqrt(st->wn2[j - 1])) {
+    st->H[(int64_t)(j - 1) * kLdh + j] = 0.0;
     st->breakdown = 1;
-    st->phase = PH_EXPM;
-    return;
   }
-  if (st->j >= st->m_target) st->phase = PH_EXPM;
+  cstore(&pb->phase, (int)((st->breakdown || j >= st->m_target) ? PH_EXPM : PH_STEP));
 }
 
 // ---- small exponential + substep controller (workgroup 0) -------------------
@@ -239,8 +329,9 @@ __device__ inline void expm_phase(const Args& a, double* lds) {
   __shared__ int s_dec;
   __shared__ double s_tau;
   State* st = a.st;
+  Pub* pb = a.pub;
   const bool fixed = a.fixed_m > 0;
-  const int m = st->m_eff;
+  const int m = cload(&pb->m_eff);
   const bool happy = st->breakdown != 0;
   const double t = st->t, beta = st->beta;
   double tau = st->tau;
@@ -279,24 +370,27 @@ __device__ inline void expm_phase(const Args& a, double* lds) {
     if (dec != D_SHRINK) break;
   }
   if (dec == D_ACCEPT) {
-    for (int i = threadIdx.x; i < m; i += kThreads) st->coef[i] = beta * st->F[i] * st->sigma[i];
+    for (int i = threadIdx.x; i < m; i += kThreads)
+      cstore(&pb->coef[i], beta * st->F[i] * st->sigma[i]);
     if (threadIdx.x == 0) {
       st->tau = tau;
-      st->last_substep = fixed ? (st->substeps + 1 >= a.fixed_substeps) : (tau >= a.h - t);
-      st->phase = PH_COMBINE;
+      const int last = fixed ? (st->substeps + 1 >= a.fixed_substeps) : (tau >= a.h - t);
+      cstore(&pb->last, last);
+      cstore(&pb->phase, (int)PH_COMBINE);
     }
   } else if (dec == D_GROW) {
     if (threadIdx.x == 0) {
       st->m_cur = min(2 * st->m_cur, a.m_max);
       st->m_target = st->m_cur;
       st->tau = tau;
-      st->sub = 0;
-      st->phase = PH_STEP;
+      cstore(&pb->upd, 0);
+      cstore(&pb->phase, (int)PH_STEP);
     }
   } else {
     if (threadIdx.x == 0) {
-      st->status = (dec == D_FAIL_NF) ? KP_STATUS_NONFINITE : KP_STATUS_NOT_CONVERGED;
-      st->phase = PH_FINISH;
+      cstore(&pb->status,
+             (int)((dec == D_FAIL_NF) ? KP_STATUS_NONFINITE : KP_STATUS_NOT_CONVERGED));
+      cstore(&pb->phase, (int)PH_FINISH);
     }
   }
   __syncthreads();
@@ -306,8 +400,9 @@ __device__ inline void expm_phase(const Args& a, double* lds) {
 __device__ inline void leader_combine(const Args& a) {
   if (threadIdx.x != 0) return;
   State* st = a.st;
+  Pub* pb = a.pub;
   const bool fixed = a.fixed_m > 0;
-  const int m = st->m_eff;
+  const int m = cload(&pb->m_eff);
   const double tau = st->tau;
   if (st->nlog < kLogMax) {
     st->log_tau[st->nlog] = tau;
@@ -317,29 +412,29 @@ __device__ inline void leader_combine(const Args& a) {
   st->err_max = fmax(st->err_max, st->err);
   st->substeps += 1;
   st->m_last = m;
-  const bool last = st->last_substep != 0;
+  const bool last = cload(&pb->last) != 0;
   st->t = last ? a.h : st->t + tau;
   if (st->breakdown) st->breakdowns += 1;
   if (last) {
-    st->phase = PH_DONE;
+    cstore(&pb->phase, (int)PH_DONE);
     return;
   }
   double tn = tau;
   if (!fixed) {
     tn = tau * tau_factor(st->omega, m);
     if (st->substeps >= a.max_substeps) {
-      st->status = KP_STATUS_NOT_CONVERGED;
-      st->phase = PH_FINISH;
+      cstore(&pb->status, (int)KP_STATUS_NOT_CONVERGED);
+      cstore(&pb->phase, (int)PH_FINISH);
       return;
     }
     tn = fmin(tn, a.h - st->t);
   }
   st->tau = tn;
-  st->j = 0;
-  st->sub = 0;
   st->breakdown = 0;
   st->m_target = fixed ? a.fixed_m : st->m_cur;
-  st->phase = PH_STEP;
+  cstore(&pb->j, 0);
+  cstore(&pb->upd, 0);
+  cstore(&pb->phase, (int)PH_STEP);
 }
 
 }  // namespace kp

@@ -1,20 +1,18 @@
 // libkrylov_phi: kernels and the C ABI declared in include/krylov_phi.h.
 //
-// Execution model (one MI355X, gfx950):
-//  * Every phase of a phi_combo call is a device function over the whole grid:
-//    stage, Arnoldi step (matvec + grouped dots, then update + norm), small
-//    exponential + controller, combine, finish.  The grid-wide reduction of a
-//    step is the paper's single global synchronisation (Algorithm 4): each
-//    workgroup writes partial sums, the last workgroup to arrive reduces them
-//    and runs the serial O(m^2) work.
-//  * KP_EXEC_PERSISTENT runs the whole call in ONE cooperative launch: the
-//    workgroups loop over the phases recorded in device memory and meet at
-//    grid barriers; the adaptive controller never returns to the host.
-//  * KP_EXEC_STREAM enqueues one kernel per phase (the kernel boundary is the
-//    barrier); it serves fixed schedules and the step-by-step test entry.
+// Execution model (one MI355X, gfx950).  A whole phi_combo call is ONE
+// cooperative launch of k_run: every workgroup loops over the phases published
+// by workgroup 0 (stage, Arnoldi step = matvec+dots then update+norm, small
+// exponential + controller, combine, finish) and meets the others at
+// grid-wide barriers.  The grid-wide reduction of an Arnoldi step is the
+// paper's single global synchronisation (Algorithm 4): every workgroup
+// publishes its partial inner products, workgroup 0 reduces them and runs the
+// O(m^2) scalar step, then releases the grid.  The adaptive substep controller
+// runs on the device; nothing returns to the host until the call is done.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,127 +24,167 @@
 
 namespace kp {
 
-constexpr int kLdsDoubles = 2 * kNmPad * kNmPad;
-static_assert(kWaves * kKStride + kKStride + 8 * kKStride + (kMMax + 8) + kWaves <= kLdsDoubles,
-              "LDS carve-up exceeds the shared buffer");
+// Carve-up of the shared phase buffer (doubles).  Streaming phases: per-wave
+// partial sums (sacc), coefficients, block-reduction scratch and the LDS copy
+// of the stencil halo rows (hl).  Leader work, after sacc is dead: group sums
+// of the partial reduction (grp), then the scalar-step work arrays (wk), and
+// the reduced inner products tv.  The small exponential uses the whole buffer
+// (it runs in a phase of its own).  The correction-matrix tables of the leader
+// live in a separate buffer for the whole launch.
+constexpr int kOffSacc = 0;
+constexpr int kOffGrp = 0;
+constexpr int kOffWk = 0;
+constexpr int kOffCoef = kWaves * kKStride;
+constexpr int kOffRed = kOffCoef + kMMax + 8;
+constexpr int kOffTv = kOffRed + kWaves;
+constexpr int kOffHl = 1536;
+constexpr int kHaloCap = 8192;            // 2 * nplanes * nx doubles at most
+constexpr int kLdsDoubles = (2 * kNmPad * kNmPad > kOffHl + kHaloCap) ? 2 * kNmPad * kNmPad
+                                                                      : kOffHl + kHaloCap;
+static_assert(kOffGrp + kRg * kKStride <= kOffCoef, "grp overlaps coef");
+static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
+static_assert(kOffTv + kKStride <= kOffHl, "tv overlaps the halo copy");
 
 struct Ctrl {
-  int phase, sub, j, m_eff, last, status, abort_;
+  int phase, j, upd, m_eff, last, status, abort_;
   double inv_mu;
 };
 
 __device__ inline void read_ctrl(const Args& a, Ctrl* c) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    State* st = a.st;
-    c->phase = __hip_atomic_load(&st->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->sub = __hip_atomic_load(&st->sub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->j = __hip_atomic_load(&st->j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->m_eff = __hip_atomic_load(&st->m_eff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->last = __hip_atomic_load(&st->last_substep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c->abort_ = (int)atomic_load_acq(a.sync + 2);
-    c->inv_mu = st->inv_mu;
+    const Pub* pb = a.pub;
+    c->phase = cload(&pb->phase);
+    c->j = cload(&pb->j);
+    c->upd = cload(&pb->upd);
+    c->m_eff = cload(&pb->m_eff);
+    c->last = cload(&pb->last);
+    c->status = cload(&pb->status);
+    c->inv_mu = cload(&pb->inv_mu);
+    c->abort_ = (int)cload(a.sync + 2);
   }
   __syncthreads();
 }
 
-__device__ inline void sync_point(const Args& a, unsigned gen0, bool leader) {
-  if (leader) {
-    leader_release(a, gen0);
-  } else if (a.persistent) {
-    wait_release(a, gen0);
-  }
-}
-
 template <typename TB>
-__device__ void run_phase(const Args& a, double* lds, const Ctrl& c) {
-  double* sacc = lds;
-  double* tv = sacc + kWaves * kKStride;
-  double* grp = tv + kKStride;
-  double* coef = grp + 8 * kKStride;
-  double* red = coef + (kMMax + 8);
-  unsigned gen0 = 0;
-  bool leader = false;
+__device__ void run_phase(const Args& a, double* lds, double* tabs, const Ctrl& c, unsigned k) {
+  double* sacc = lds + kOffSacc;
+  double* grp = lds + kOffGrp;
+  double* wk = lds + kOffWk;
+  double* coef = lds + kOffCoef;
+  double* red = lds + kOffRed;
+  double* tv = lds + kOffTv;
+  double* hl = lds + kOffHl;
+  const bool lead = blockIdx.x == 0;
   switch (c.phase) {
     case PH_STAGE:
       stage_pass(a, red);
-      leader = arrive(a, &gen0);
-      if (leader) leader_stage(a);
-      sync_point(a, gen0, leader);
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        leader_stage(a, red);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
+      }
       break;
     case PH_STEP:
-      if (c.sub == 0) {
-        matvec_dots_pass<TB>(a, c.j, c.inv_mu, sacc);
-        leader = arrive(a, &gen0);
-        if (leader) {
-          reduce_partials(a, 2 * c.j + 3, tv, grp);
-          scalar_step(a, c.j, tv);
-        }
-        sync_point(a, gen0, leader);
-      } else {
-        for (int k = threadIdx.x; k < c.j + 2; k += kThreads) coef[k] = a.st->coef[k];
+      // the update that produces x_j (coefficients of the previous scalar
+      // step), then the matvec + grouped dots of step j: one grid-wide sync
+      if (c.upd) {
+        for (int i = threadIdx.x; i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
         __syncthreads();
-        update_pass<TB>(a, c.j, coef, red);
-        leader = arrive(a, &gen0);
-        if (leader) {
-          reduce_partials(a, 1, tv, grp);
-          leader_norm(a, c.j, tv[0]);
-        }
-        sync_point(a, gen0, leader);
+        update_pass<TB>(a, c.j - 1, coef, red, false);
+        flag_publish(a, k);
+        flag_wait_neighbours(a, k);
+      }
+      if (a.halo_lds)
+        matvec_dots_pass<TB, true>(a, c.j, c.inv_mu, sacc, hl);
+      else
+        matvec_dots_pass<TB, false>(a, c.j, c.inv_mu, sacc, hl);
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        reduce_partials(a, 2 * c.j + 3, tv, grp);
+        scalar_step(a, c.j, tv, tabs, wk);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
+      }
+      break;
+    case PH_CLOSE:
+      for (int i = threadIdx.x; i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
+      __syncthreads();
+      update_pass<TB>(a, c.j - 1, coef, red, true);
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        reduce_partials(a, 1, tv, grp);
+        leader_close(a, tv[0]);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
       }
       break;
     case PH_EXPM:
-      if (!a.persistent) {
-        if (blockIdx.x == 0) expm_phase(a, lds);
-        break;
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        expm_phase(a, lds);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
       }
-      if (blockIdx.x == 0) expm_phase(a, lds);
-      leader = arrive(a, &gen0);
-      sync_point(a, gen0, leader);
       break;
     case PH_COMBINE:
-      for (int k = threadIdx.x; k < c.m_eff; k += kThreads) coef[k] = a.st->coef[k];
+      for (int i = threadIdx.x; i < c.m_eff; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
       __syncthreads();
       combine_pass<TB>(a, c.m_eff, coef, c.last != 0);
-      leader = arrive(a, &gen0);
-      if (leader) leader_combine(a);
-      sync_point(a, gen0, leader);
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        leader_combine(a);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
+      }
       break;
     case PH_FINISH:
       finish_pass(a, c.status == KP_STATUS_NONFINITE);
-      leader = arrive(a, &gen0);
-      if (leader && threadIdx.x == 0) a.st->phase = PH_DONE;
-      sync_point(a, gen0, leader);
+      bar_arrive(a);
+      if (lead) {
+        bar_gather(a, k);
+        if (threadIdx.x == 0) cstore(&a.pub->phase, (int)PH_DONE);
+        bar_release(a, k);
+      } else {
+        bar_wait(a, k);
+      }
       break;
     default:
       break;
   }
 }
 
-// Whole call in one cooperative launch.
+// The whole call (or, for the step-by-step entry, the steps up to stop_j).
 template <typename TB>
-__global__ __launch_bounds__(kThreads) void k_persistent(Args a) {
+__global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
   __shared__ double lds[kLdsDoubles];
+  __shared__ double tabs[kTabDoubles];
   __shared__ Ctrl c;
+  __shared__ unsigned s_k;
+  if (threadIdx.x == 0) s_k = cload(a.sync + 1);   // barriers released by earlier launches
+  if (blockIdx.x == 0) load_tables(a, tabs);
+  __syncthreads();
+  unsigned k = s_k;
   for (;;) {
     read_ctrl(a, &c);
     if (c.phase == PH_DONE || c.abort_) break;
-    run_phase<TB>(a, lds, c);
+    if (arnoldi_only &&
+        (c.phase >= PH_EXPM || (c.phase == PH_STEP && c.j >= a.stop_j)))
+      break;
+    ++k;
+    run_phase<TB>(a, lds, tabs, c, k);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && atomic_load_acq(a.sync + 2) != 0u)
-    a.st->status = KP_STATUS_ABORTED;
-}
-
-// One phase per launch; a launch whose phase is not due does nothing.
-template <typename TB, int PH, int SUB>
-__global__ __launch_bounds__(kThreads) void k_phase(Args a) {
-  __shared__ double lds[kLdsDoubles];
-  __shared__ Ctrl c;
-  read_ctrl(a, &c);
-  if (c.phase != PH) return;
-  if (PH == PH_STEP && c.sub != SUB) return;
-  run_phase<TB>(a, lds, c);
 }
 
 // Reset of the call state; the Hessenberg and correction matrices are zeroed
@@ -158,28 +196,31 @@ __global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
     st->Lm[i] = 0.0;
     st->Minv[i] = 0.0;
   }
+  for (int i = threadIdx.x; i < kMMax + 2; i += blockDim.x) a.pub->coef[i] = 0.0;
+  for (int i = threadIdx.x; i < a.nwg * kFlagStride; i += blockDim.x) a.flags[i] = 0u;
   if (threadIdx.x != 0) return;
   a.sync[0] = 0u;
   a.sync[1] = 0u;
   a.sync[2] = 0u;
-  st->phase = PH_STAGE;
-  st->sub = 0;
-  st->status = KP_STATUS_OK;
-  st->j = 0;
+  Pub* pb = a.pub;
+  pb->phase = PH_STAGE;
+  pb->upd = 0;
+  pb->j = 0;
+  pb->m_eff = 0;
+  pb->last = 0;
+  pb->status = KP_STATUS_OK;
+  pb->inv_mu = 1.0;
   st->m_target = m_target;
   st->m_cur = m_target;
-  st->m_eff = 0;
   st->breakdown = 0;
   st->fallback_cur = 0;
-  st->last_substep = 0;
   st->substeps = st->rejected = st->arnoldi_steps = st->expm_evals = 0;
-  st->n_fallback = st->breakdowns = st->nlog = st->zero = st->aborted = 0;
+  st->n_fallback = st->breakdowns = st->nlog = st->zero = 0;
   st->m_last = 0;
   st->t = 0.0;
   st->tau = (a.fixed_m > 0) ? a.h / (double)a.fixed_substeps : a.h;
   st->beta = 0.0;
   st->mu = 1.0;
-  st->inv_mu = 1.0;
   st->err_max = st->omega = st->err = st->last_nrm2 = 0.0;
 }
 
@@ -196,6 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double ta
 // ============================================================================
 
 using kp::Args;
+using kp::Pub;
 using kp::State;
 
 struct kp_ctx {
@@ -210,12 +252,19 @@ struct kp_ctx {
   size_t u_bytes = 0;
   double* part = nullptr;
   size_t part_bytes = 0;
+  double* hx = nullptr;
+  size_t hx_bytes = 0;
+  unsigned* flags = nullptr;
+  size_t flags_bytes = 0;
   unsigned* sync = nullptr;
   State* st = nullptr;
+  Pub* pub = nullptr;
   double* ex = nullptr;
+  double* tx = nullptr;
   int occ[2] = {-1, -1};
   Args last{};
   int have_begin = 0;
+  int arn_target = 0;
   char err[512] = {0};
 };
 
@@ -235,7 +284,7 @@ int hip_fail(kp_ctx* c, hipError_t e, const char* what) {
 int check_config(const kp_config* c) {
   if (c->orth < 0 || c->orth > KP_ORTH_H_NCWY) return KP_EINVAL;
   if (c->basis_dtype != KP_BASIS_F64 && c->basis_dtype != KP_BASIS_F32) return KP_EINVAL;
-  if (c->exec_mode != KP_EXEC_PERSISTENT && c->exec_mode != KP_EXEC_STREAM) return KP_EINVAL;
+  if (c->reserved0 != 0) return KP_EINVAL;
   if (c->max_substeps < 0 || c->fixed_m < 0 || c->fixed_m > KP_MMAX) return KP_EINVAL;
   if (c->fixed_m > 0 && c->fixed_substeps < 1) return KP_EINVAL;
   if (c->fixed_substeps < 0) return KP_EINVAL;
@@ -266,8 +315,9 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
     if (!std::isfinite(v)) return KP_EINVAL;
   if (A->kind == KP_OP_ALLEN_CAHN && !A->field0) return KP_EINVAL;
   if (A->kind == KP_OP_BRUSSELATOR && (!A->field0 || !A->field1)) return KP_EINVAL;
+  const int nplanes = A->kind == KP_OP_BRUSSELATOR ? 2 : 1;
   const int64_t npt = (int64_t)A->nx * A->ny;
-  const int64_t N = npt * (A->kind == KP_OP_BRUSSELATOR ? 2 : 1);
+  const int64_t N = npt * nplanes;
   if (N > (int64_t)1 << 30) return KP_EINVAL;
   if (p < 0 || p > KP_PMAX) return KP_EINVAL;
   if (ldb < N) return KP_EINVAL;
@@ -290,19 +340,22 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.f1 = A->field1;
   r.out = out;
   r.N = (int)N;
-  r.L = (int)(N + p);
   r.p = p;
   r.npt = (int)npt;
   r.nx = A->nx;
   r.ny = A->ny;
-  r.ld = ((int64_t)r.L + 63) / 64 * 64;
-  r.npairs = r.ld / 2;
+  r.nplanes = nplanes;
+  r.npt_pad = (npt + kp::kPlaneAlign - 1) / kp::kPlaneAlign * kp::kPlaneAlign;
+  r.tail_off = r.npt_pad * nplanes;
+  r.ld = r.tail_off + kp::kTailPad;
   r.kind = A->kind;
   r.transpose = A->transpose ? 1 : 0;
   r.cx = A->nu / (A->dx * A->dx);
   r.cy = A->nu / (A->dy * A->dy);
   r.cx2 = A->nu2 / (A->dx * A->dx);
   r.cy2 = A->nu2 / (A->dy * A->dy);
+  r.inv_nx = 1.0 / (double)A->nx;
+  r.halo_lds = (2 * nplanes * (int64_t)A->nx <= kp::kHaloCap) ? 1 : 0;
   r.adx = A->ax / (2.0 * A->dx);
   r.ady = A->ay / (2.0 * A->dy);
   r.react = A->react;
@@ -313,7 +366,7 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.fixed_substeps = cfg.fixed_m > 0 ? cfg.fixed_substeps : 0;
   r.max_substeps = cfg.max_substeps > 0 ? cfg.max_substeps : 2000;
   r.m_max = m_max;
-  r.persistent = cfg.exec_mode == KP_EXEC_PERSISTENT ? 1 : 0;
+  r.stop_j = INT_MAX;
   r.basis_f32 = cfg.basis_dtype == KP_BASIS_F32 ? 1 : 0;
   r.h = h;
   r.tol = tol > 0.0 ? tol : 1.0;
@@ -328,7 +381,7 @@ int occupancy(kp_ctx* ctx, int which) {
   if (ctx->occ[which] < 0) {
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void*>(&kp::k_persistent<TB>), kp::kThreads, 0);
+        &occ, reinterpret_cast<const void*>(&kp::k_run<TB>), kp::kThreads, 0);
     if (e != hipSuccess) return -1;
     ctx->occ[which] = occ;
   }
@@ -366,7 +419,21 @@ int grow(kp_ctx* ctx, void** p, size_t* have, size_t need) {
   return KP_OK;
 }
 
-// Allocate the workspace for a problem and finish Args (grid geometry).
+// Grid geometry: workgroup b owns rows [b*rows, (b+1)*rows) of every plane.
+// At least one full sub-tile (kThreads * kR pairs) of elements per workgroup,
+// at most one workgroup per co-resident slot; an even row count when nx is
+// odd keeps every segment start even (pair alignment).
+void geometry(int ncu_slots, Args* a) {
+  const int64_t per_wg_min = (int64_t)kp::kThreads * kp::kR * 2;
+  int64_t rows = (per_wg_min + (int64_t)a->nx * a->nplanes - 1) / ((int64_t)a->nx * a->nplanes);
+  rows = std::max<int64_t>(rows, (a->ny + ncu_slots - 1) / ncu_slots);
+  rows = std::max<int64_t>(1, std::min<int64_t>(rows, a->ny));
+  if ((a->nx & 1) && (rows & 1) && rows < a->ny) ++rows;
+  a->rows_per_wg = (int)rows;
+  a->nwg = (int)((a->ny + rows - 1) / rows);
+}
+
+// Allocate the workspace for a problem and finish Args.
 int prepare(kp_ctx* ctx, Args* a) {
   int rc = device_setup(ctx);
   if (rc) return rc;
@@ -378,61 +445,57 @@ int prepare(kp_ctx* ctx, Args* a) {
     return rc;
   const int occ = a->basis_f32 ? occupancy<float>(ctx, 1) : occupancy<double>(ctx, 0);
   if (occ <= 0) {
-    snprintf(ctx->err, sizeof(ctx->err), "persistent kernel does not fit on a CU");
+    snprintf(ctx->err, sizeof(ctx->err), "the persistent kernel does not fit on a CU");
     return KP_EHIP;
   }
-  const int64_t per_wg = (int64_t)kp::kThreads * kp::kR;
-  int64_t nwg = (a->npairs + per_wg - 1) / per_wg;
-  nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, (int64_t)ctx->ncu * occ));
-  a->nwg = (int)nwg;
-  a->ppw = (a->npairs + nwg - 1) / nwg;
+  geometry(ctx->ncu * occ, a);
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->part), &ctx->part_bytes,
-                 (size_t)nwg * kp::kKStride * sizeof(double))))
+                 (size_t)a->nwg * kp::kKStride * sizeof(double))))
+    return rc;
+  if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->hx), &ctx->hx_bytes,
+                 (size_t)a->nwg * a->nplanes * 2 * a->nx * sizeof(double))))
+    return rc;
+  if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->flags), &ctx->flags_bytes,
+                 (size_t)a->nwg * kp::kFlagStride * sizeof(unsigned))))
     return rc;
   if (!ctx->st) {
     KP_HIP(ctx, hipMalloc(&ctx->st, sizeof(State)));
+    KP_HIP(ctx, hipMalloc(&ctx->pub, sizeof(Pub)));
     KP_HIP(ctx, hipMalloc(&ctx->sync, 64));
     KP_HIP(ctx, hipMalloc(&ctx->ex, sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad));
+    KP_HIP(ctx, hipMalloc(&ctx->tx, sizeof(double) * kp::kTailPad));
   }
   a->V = ctx->V;
   a->u = ctx->u;
   a->part = ctx->part;
+  a->hx = ctx->hx;
+  a->tx = ctx->tx;
+  a->flags = ctx->flags;
   a->sync = ctx->sync;
   a->st = ctx->st;
+  a->pub = ctx->pub;
   a->ex = ctx->ex;
   a->wait_ticks = ctx->wait_ticks;
   return KP_OK;
 }
 
-template <typename TB, int PH, int SUB>
-int launch_phase(kp_ctx* ctx, const Args& a, int grid) {
-  hipLaunchKernelGGL((kp::k_phase<TB, PH, SUB>), dim3(grid), dim3(kp::kThreads), 0,
-                     ctx->stream, a);
-  KP_HIP(ctx, hipGetLastError());
+template <typename TB>
+int launch_run(kp_ctx* ctx, Args a, int arnoldi_only) {
+  void* args[] = {&a, &arnoldi_only};
+  KP_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&kp::k_run<TB>),
+                                         dim3(a.nwg), dim3(kp::kThreads), args, 0,
+                                         ctx->stream));
   return KP_OK;
 }
 
-template <typename TB>
-int run_stream(kp_ctx* ctx, const Args& a) {
-  int rc;
-  if ((rc = launch_phase<TB, kp::PH_STAGE, 0>(ctx, a, a.nwg))) return rc;
-  for (int s = 0; s < a.fixed_substeps; ++s) {
-    for (int j = 0; j < a.fixed_m; ++j) {
-      if ((rc = launch_phase<TB, kp::PH_STEP, 0>(ctx, a, a.nwg))) return rc;
-      if ((rc = launch_phase<TB, kp::PH_STEP, 1>(ctx, a, a.nwg))) return rc;
-    }
-    if ((rc = launch_phase<TB, kp::PH_EXPM, 0>(ctx, a, 1))) return rc;
-    if ((rc = launch_phase<TB, kp::PH_COMBINE, 0>(ctx, a, a.nwg))) return rc;
-  }
-  return launch_phase<TB, kp::PH_FINISH, 0>(ctx, a, a.nwg);
+int launch(kp_ctx* ctx, const Args& a, int arnoldi_only) {
+  return a.basis_f32 ? launch_run<float>(ctx, a, arnoldi_only)
+                     : launch_run<double>(ctx, a, arnoldi_only);
 }
 
-template <typename TB>
-int run_persistent(kp_ctx* ctx, Args a) {
-  void* args[] = {&a};
-  KP_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&kp::k_persistent<TB>),
-                                         dim3(a.nwg), dim3(kp::kThreads), args, 0,
-                                         ctx->stream));
+int launch_init(kp_ctx* ctx, const Args& a, int m_target) {
+  hipLaunchKernelGGL(kp::k_init, dim3(1), dim3(256), 0, ctx->stream, a, m_target);
+  KP_HIP(ctx, hipGetLastError());
   return KP_OK;
 }
 
@@ -440,10 +503,12 @@ int fill_info(kp_ctx* ctx, kp_info* info) {
   KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   State h;
   KP_HIP(ctx, hipMemcpy(&h, ctx->st, offsetof(State, sigma), hipMemcpyDeviceToHost));
+  Pub pb;
+  KP_HIP(ctx, hipMemcpy(&pb, ctx->pub, sizeof(Pub), hipMemcpyDeviceToHost));
   unsigned flags[3] = {0, 0, 0};
   KP_HIP(ctx, hipMemcpy(flags, ctx->sync, sizeof(flags), hipMemcpyDeviceToHost));
   std::memset(info, 0, sizeof(*info));
-  info->status = flags[2] ? KP_STATUS_ABORTED : h.status;
+  info->status = flags[2] ? KP_STATUS_ABORTED : pb.status;
   info->substeps = h.substeps;
   info->rejected = h.rejected;
   info->arnoldi_steps = h.arnoldi_steps;
@@ -462,7 +527,7 @@ int fill_info(kp_ctx* ctx, kp_info* info) {
 
 extern "C" {
 
-int kp_version(void) { return 10000; }
+int kp_version(void) { return 10100; }
 
 const char* kp_strerror(int code) {
   switch (code) {
@@ -505,12 +570,10 @@ int kp_set_config(kp_ctx* ctx, const kp_config* cfg) {
 int kp_destroy(kp_ctx* ctx) {
   if (!ctx) return KP_EINVAL;
   if (ctx->ncu > 0) hipStreamSynchronize(ctx->stream);
-  if (ctx->V) hipFree(ctx->V);
-  if (ctx->u) hipFree(ctx->u);
-  if (ctx->part) hipFree(ctx->part);
-  if (ctx->st) hipFree(ctx->st);
-  if (ctx->sync) hipFree(ctx->sync);
-  if (ctx->ex) hipFree(ctx->ex);
+  void* bufs[] = {ctx->V,  ctx->u,    ctx->part, ctx->hx, ctx->flags,
+                  ctx->st, ctx->pub, ctx->sync, ctx->ex, ctx->tx};
+  for (void* b : bufs)
+    if (b) hipFree(b);
   delete ctx;
   return KP_OK;
 }
@@ -520,17 +583,10 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_
   Args a;
   int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, out, true, &a);
   if (rc) return rc;
-  if (ctx->cfg.exec_mode == KP_EXEC_STREAM && ctx->cfg.fixed_m == 0) return KP_EUNSUPPORTED;
   if ((rc = prepare(ctx, &a))) return rc;
   const int m0 = a.fixed_m > 0 ? a.fixed_m : std::min(16, a.m_max);
-  hipLaunchKernelGGL(kp::k_init, dim3(1), dim3(256), 0, ctx->stream, a, m0);
-  KP_HIP(ctx, hipGetLastError());
-  if (a.persistent) {
-    rc = a.basis_f32 ? run_persistent<float>(ctx, a) : run_persistent<double>(ctx, a);
-  } else {
-    rc = a.basis_f32 ? run_stream<float>(ctx, a) : run_stream<double>(ctx, a);
-  }
-  if (rc) return rc;
+  if ((rc = launch_init(ctx, a, m0))) return rc;
+  if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;
   ctx->have_begin = 0;
   if (info) return fill_info(ctx, info);
@@ -560,33 +616,23 @@ int kp_arnoldi_begin(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, in
   int rc = build_args(ctx, A, B, p, ldb, 1.0, 1.0, m_max, nullptr, false, &a);
   ctx->cfg = saved;
   if (rc) return rc;
-  a.persistent = 0;
   if ((rc = prepare(ctx, &a))) return rc;
-  hipLaunchKernelGGL(kp::k_init, dim3(1), dim3(256), 0, ctx->stream, a, m_max);
-  KP_HIP(ctx, hipGetLastError());
-  rc = a.basis_f32 ? launch_phase<float, kp::PH_STAGE, 0>(ctx, a, a.nwg)
-                   : launch_phase<double, kp::PH_STAGE, 0>(ctx, a, a.nwg);
-  if (rc) return rc;
+  a.stop_j = 0;
+  if ((rc = launch_init(ctx, a, m_max))) return rc;
+  if ((rc = launch(ctx, a, 1))) return rc;
   ctx->last = a;
   ctx->have_begin = 1;
+  ctx->arn_target = 0;
   return KP_OK;
 }
 
 int kp_arnoldi_step(kp_ctx* ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0) return KP_EINVAL;
   if (!ctx->have_begin) return KP_ESTATE;
-  const Args& a = ctx->last;
-  for (int s = 0; s < nsteps; ++s) {
-    int rc;
-    if (a.basis_f32) {
-      if ((rc = launch_phase<float, kp::PH_STEP, 0>(ctx, a, a.nwg))) return rc;
-      if ((rc = launch_phase<float, kp::PH_STEP, 1>(ctx, a, a.nwg))) return rc;
-    } else {
-      if ((rc = launch_phase<double, kp::PH_STEP, 0>(ctx, a, a.nwg))) return rc;
-      if ((rc = launch_phase<double, kp::PH_STEP, 1>(ctx, a, a.nwg))) return rc;
-    }
-  }
-  return KP_OK;
+  ctx->arn_target = std::min(ctx->arn_target + nsteps, ctx->last.m_max);
+  Args a = ctx->last;
+  a.stop_j = ctx->arn_target;
+  return launch(ctx, a, 1);
 }
 
 int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host,
@@ -598,7 +644,9 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
   std::vector<char> buf(sizeof(State));
   State* h = reinterpret_cast<State*>(buf.data());
   KP_HIP(ctx, hipMemcpy(h, ctx->st, sizeof(State), hipMemcpyDeviceToHost));
-  const int j = h->j;
+  Pub pb;
+  KP_HIP(ctx, hipMemcpy(&pb, ctx->pub, sizeof(Pub), hipMemcpyDeviceToHost));
+  const int j = pb.j;
   if (j_host) *j_host = j;
   if (beta_host) *beta_host = h->beta;
   if (flags_host) {
@@ -612,7 +660,7 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
   }
   if (V_host) {
     const int ncol = j + 1;
-    const size_t L = (size_t)a.L;
+    const size_t L = (size_t)a.N + a.p;
     const size_t esz = a.basis_f32 ? sizeof(float) : sizeof(double);
     std::vector<char> raw((size_t)a.ld * ncol * esz);
     KP_HIP(ctx, hipMemcpy(raw.data(), ctx->V, raw.size(), hipMemcpyDeviceToHost));
@@ -620,11 +668,15 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
       double scale;
       if (c < j) scale = h->sigma[c];
       else scale = (h->last_nrm2 > 0.0 && !h->breakdown) ? 1.0 / std::sqrt(h->last_nrm2) : 0.0;
-      for (size_t e = 0; e < L; ++e) {
-        const double v = a.basis_f32 ? (double)reinterpret_cast<float*>(raw.data())[(size_t)c * a.ld + e]
-                                     : reinterpret_cast<double*>(raw.data())[(size_t)c * a.ld + e];
-        V_host[(size_t)c * L + e] = v * scale;
-      }
+      auto at = [&](int64_t e) {
+        return a.basis_f32 ? (double)reinterpret_cast<float*>(raw.data())[(size_t)c * a.ld + e]
+                           : reinterpret_cast<double*>(raw.data())[(size_t)c * a.ld + e];
+      };
+      for (int s = 0; s < a.nplanes; ++s)
+        for (int64_t q = 0; q < a.npt; ++q)
+          V_host[(size_t)c * L + (size_t)s * a.npt + q] = at(s * a.npt_pad + q) * scale;
+      for (int k = 0; k < a.p; ++k)
+        V_host[(size_t)c * L + a.N + k] = at(a.tail_off + k) * scale;
     }
   }
   return KP_OK;
@@ -638,8 +690,10 @@ int kp_expm_hbar(kp_ctx* ctx, const double* H_host, int32_t ldh, int32_t m, doub
   if (rc) return rc;
   if (!ctx->st) {
     KP_HIP(ctx, hipMalloc(&ctx->st, sizeof(State)));
+    KP_HIP(ctx, hipMalloc(&ctx->pub, sizeof(Pub)));
     KP_HIP(ctx, hipMalloc(&ctx->sync, 64));
     KP_HIP(ctx, hipMalloc(&ctx->ex, sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad));
+    KP_HIP(ctx, hipMalloc(&ctx->tx, sizeof(double) * kp::kTailPad));
   }
   std::vector<double> Hs((size_t)kp::kLdh * kp::kMMax, 0.0);
   for (int c = 0; c < m; ++c)

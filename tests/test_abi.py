@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_constants_match_header():
     text = open(HEADER).read()
     for name in ("KP_OK", "KP_EINVAL", "KP_EUNSUPPORTED", "KP_ORTH_H_GSMGS", "KP_ORTH_H_NCWY",
-                 "KP_OP_BRUSSELATOR", "KP_BASIS_F32", "KP_EXEC_STREAM", "KP_MMAX", "KP_PMAX",
+                 "KP_OP_BRUSSELATOR", "KP_BASIS_F32", "KP_MMAX", "KP_PMAX",
                  "KP_STATUS_NONFINITE"):
         m = re.search(rf"#define\s+{name}\s+(-?\d+)", text)
         assert m and int(m.group(1)) == getattr(_lib, name), name
@@ -46,7 +46,7 @@ def test_struct_layouts_match_header_sizes():
 
 def test_version_and_strerror():
     lib = _lib.load()
-    assert lib.kp_version() == 10000
+    assert lib.kp_version() == 10100
     assert lib.kp_strerror(-1) == b"invalid argument"
     assert lib.kp_strerror(12345) == b"unknown error"
 
@@ -61,7 +61,7 @@ def _ctx(**kw):
     return lib, h, rc
 
 
-@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("exec_mode", -1),
+@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("reserved0", 1),
                                        ("fixed_m", 65), ("max_substeps", -2)])
 def test_create_rejects_bad_config(field, val):
     lib, h, rc = _ctx(**{field: val})
@@ -114,16 +114,6 @@ def test_phi_combo_rejects_bad_arguments(opkw, args):
         rc = lib.kp_phi_combo(h, ctypes.byref(op), a["B"], a["p"], a["ldb"], a["h"], a["tol"],
                               a["m_max"], a["out"], None)
         assert rc == _lib.KP_EINVAL
-    finally:
-        lib.kp_destroy(h)
-
-
-def test_stream_mode_needs_fixed_schedule():
-    lib, h, rc = _ctx(exec_mode=1)
-    try:
-        op = _op()
-        rc = lib.kp_phi_combo(h, ctypes.byref(op), FAKE, 2, 64, 0.1, 1e-8, 10, FAKE2, None)
-        assert rc == _lib.KP_EUNSUPPORTED
     finally:
         lib.kp_destroy(h)
 

@@ -122,14 +122,13 @@ FIXED = [
 
 
 @pytest.mark.parametrize("case", FIXED)
-@pytest.mark.parametrize("exec_mode", ["persistent", "stream"])
 @pytest.mark.parametrize("orth", ["h-gsmgs", "h-cwy", "h-ncwy"])
-def test_phi_combo_fixed_schedule(case, exec_mode, orth):
+def test_phi_combo_fixed_schedule(case, orth):
     kind, nx, ny, p, m, nsub = case
-    say(f"fixed kind={kind} {nx}x{ny} p={p} m={m} nsub={nsub} {exec_mode} {orth}")
+    say(f"fixed kind={kind} {nx}x{ny} p={p} m={m} nsub={nsub} {orth}")
     pr = W.random_problem(11, kind=kind, nx=nx, ny=ny, p=p, h=0.05, with_diag=True)
     op, B = dev(pr)
-    with kp.Context(orth=orth, exec_mode=exec_mode, fixed_m=m, fixed_substeps=nsub) as ctx:
+    with kp.Context(orth=orth, fixed_m=m, fixed_substeps=nsub) as ctx:
         y, info = ctx.phi_combo(op, B, pr.h, m_max=m, info=True)
         sched = ctx.schedule()
     ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=m, fixed_substeps=nsub, m_max=m)
