@@ -50,7 +50,7 @@ __device__ inline double lin_at(const Args& a, const Lin& L, int i, int k) {
 
 // LDS tile (kNmPad x kNmPad) <- linear combination, zero outside n x n.
 __device__ inline void load_lin(const Args& a, const Lin& L, int n, double* s) {
-  for (int idx = threadIdx.x; idx < kNmPad * kNmPad; idx += kThreads) {
+  for (int idx = kp_tid(); idx < kNmPad * kNmPad; idx += kThreads) {
     const int i = idx / kNmPad, k = idx - i * kNmPad;
     s[idx] = (i < n && k < n) ? lin_at(a, L, i, k) : 0.0;
   }
@@ -65,7 +65,7 @@ __device__ inline void matmul(const Args& a, int n, const Lin& A, const Lin& B,
   __syncthreads();
   const int nb = (n + 3) >> 2;
   double* C = slot(a, cs);
-  for (int blk = threadIdx.x; blk < nb * nb; blk += kThreads) {
+  for (int blk = kp_tid(); blk < nb * nb; blk += kThreads) {
     const int bi = blk / nb, bj = blk - bi * nb;
     double acc[4][4];
 #pragma unroll
@@ -101,7 +101,7 @@ __device__ inline void matmul(const Args& a, int n, const Lin& A, const Lin& B,
 // with partial pivoting, then back substitution; R is left in sB.
 __device__ inline void lu_solve(int n, double* sA, double* sB) {
   __shared__ int s_piv;
-  const int tid = threadIdx.x;
+  const int tid = kp_tid();
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {                      // pivot search by wave 0
       double best = -1.0;
@@ -171,7 +171,7 @@ __device__ inline void expm_hbar(const Args& a, const double* H, int ldh, int m,
   double* sA = lds;
   double* sB = lds + kNmPad * kNmPad;
   const int n = m + 1;
-  const int tid = threadIdx.x;
+  const int tid = kp_tid();
   double b[14];
   pade13_coeffs(b);
   // X = tau * Hbar into slot 0; column sums for the 1-norm

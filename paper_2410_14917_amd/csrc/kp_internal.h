@@ -22,6 +22,15 @@
 
 namespace kp {
 
+// threadIdx.x, re-read at every use (an opaque move), so that per-lane values
+// derived from it are computed where they are used and are not hoisted out of
+// the persistent kernel's phase loop (where they would stay live throughout).
+__device__ __forceinline__ int kp_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
 constexpr int kThreads = 512;             // threads per workgroup (one per CU)
 constexpr int kWaves = kThreads / 64;
 constexpr int kMMax = KP_MMAX;
@@ -167,7 +176,7 @@ __device__ inline double wave_max(double v) {
 // Sum over the workgroup; every thread gets the result.  `red` holds kWaves
 // doubles of LDS.  Deterministic (fixed order).
 __device__ inline double block_sum(double v, double* red) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
   v = wave_sum(v);
   __syncthreads();
   if (lane == 0) red[wv] = v;
@@ -180,7 +189,7 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 __device__ inline double block_max(double v, double* red) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
   v = wave_max(v);
   __syncthreads();
   if (lane == 0) red[wv] = v;
@@ -194,53 +203,124 @@ __device__ inline double block_max(double v, double* red) {
 
 // ---- grid-wide synchronisation ---------------------------------------------
 //
+// Sync block (64 bytes): arrival counter (u32 word 0), release word (u64 at
+// byte 8: barrier number in the high half, the packed control of the phase it
+// opens in the low half), abort flag (u32 word 4).
+//
 // Barrier number k (counted identically by every workgroup): every workgroup
 // increments the arrival counter; workgroup 0 waits until it reads k * nwg,
-// does the serial work of the phase, publishes, and sets the release counter
-// to k; the others wait until they read k.  Each wait is bounded by
-// a.wait_ticks of the steady counter: past it the abort flag is raised and all
-// workgroups leave their main loop at the next check, so a launch always ends.
+// does the serial work of the phase, and stores the release word (k, control);
+// the others wait until they read k and take the control of the next phase
+// from the same word.  Each wait is bounded by a.wait_ticks of the steady
+// counter: past it the abort flag is raised and all workgroups leave their
+// main loop, so a launch always ends.
+
+constexpr int kSyncArrive = 0;
+constexpr int kSyncAbort = 4;
+
+// Control of one phase, uniform across the grid.
+struct Ctl {
+  int phase;
+  int j;        // completed Arnoldi steps of the current substep
+  int upd;      // the update producing x_j is still pending (PH_STEP/CLOSE)
+  int m_eff;    // Krylov dimension available (small exponential, combine)
+  int last;     // the accepted substep ends at h
+  int status;
+};
+
+__device__ inline unsigned ctl_pack(const Ctl& c) {
+  return (unsigned)c.phase | ((unsigned)c.j << 3) | ((unsigned)c.upd << 10) |
+         ((unsigned)c.m_eff << 11) | ((unsigned)c.last << 18) | ((unsigned)c.status << 19);
+}
+__device__ inline Ctl ctl_unpack(unsigned w) {
+  Ctl c;
+  c.phase = (int)(w & 7u);
+  c.j = (int)((w >> 3) & 127u);
+  c.upd = (int)((w >> 10) & 1u);
+  c.m_eff = (int)((w >> 11) & 127u);
+  c.last = (int)((w >> 18) & 1u);
+  c.status = (int)((w >> 19) & 3u);
+  return c;
+}
+
+__device__ inline unsigned long long* release_word(const Args& a) {
+  return reinterpret_cast<unsigned long long*>(a.sync + 2);
+}
 
 __device__ inline void wait_all_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
+__device__ inline bool aborted(const Args& a) { return cload(a.sync + kSyncAbort) != 0u; }
+
+__device__ inline bool wait_expired(const Args& a, int64_t t0) {
+  if (wall_clock64() - t0 > a.wait_ticks) {
+    cstore(a.sync + kSyncAbort, 1u);
+    return true;
+  }
+  return false;
+}
+
+// Spin until *ctr >= target (false: the launch is aborting).
 __device__ inline bool spin_until(const Args& a, const unsigned* ctr, unsigned target) {
   if (cload(ctr) >= target) return true;
   const int64_t t0 = wall_clock64();
   for (unsigned it = 1;; ++it) {
     if (cload(ctr) >= target) return true;
-    if ((it & 31u) == 0u) {
-      if (cload(a.sync + 2) != 0u) return false;
-      if (wall_clock64() - t0 > a.wait_ticks) {
-        cstore(a.sync + 2, 1u);
-        return false;
-      }
-    }
+    if ((it & 31u) == 0u && (aborted(a) || wait_expired(a, t0))) return false;
   }
 }
 
 __device__ inline void bar_arrive(const Args& a) {
   wait_all_stores();
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(a.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (kp_tid() == 0)
+    __hip_atomic_fetch_add(a.sync + kSyncArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup 0: wait for every arrival at barrier k.
-__device__ inline void bar_gather(const Args& a, unsigned k) {
-  if (threadIdx.x == 0) spin_until(a, a.sync, k * (unsigned)a.nwg);
+// Workgroup 0: wait for every arrival at barrier k.  *ok (LDS) = false when
+// the launch is aborting.
+__device__ inline void bar_gather(const Args& a, unsigned k, int* ok) {
+  if (kp_tid() == 0) *ok = spin_until(a, a.sync + kSyncArrive, k * (unsigned)a.nwg) ? 1 : 0;
   __syncthreads();
 }
 
-// Workgroup 0: open barrier k after its coherent stores completed.
-__device__ inline void bar_release(const Args& a, unsigned k) {
+// Workgroup 0: open barrier k, announcing the control of the next phase,
+// after its coherent stores completed.  The control is mirrored in the Pub
+// block for the host.
+__device__ inline void bar_release(const Args& a, unsigned k, const Ctl& nxt, Pub* pb) {
   wait_all_stores();
   __syncthreads();
-  if (threadIdx.x == 0) cstore(a.sync + 1, k);
+  if (kp_tid() == 0) {
+    cstore(&pb->phase, nxt.phase);
+    cstore(&pb->j, nxt.j);
+    cstore(&pb->upd, nxt.upd);
+    cstore(&pb->m_eff, nxt.m_eff);
+    cstore(&pb->last, nxt.last);
+    cstore(&pb->status, nxt.status);
+    cstore(release_word(a), ((unsigned long long)k << 32) | ctl_pack(nxt));
+  }
 }
 
-// Other workgroups: wait for the release of barrier k.
-__device__ inline void bar_wait(const Args& a, unsigned k) {
-  if (threadIdx.x == 0) spin_until(a, a.sync + 1, k);
+// Other workgroups: wait for the release of barrier k and take the control of
+// the next phase (cur, LDS); *ok = false when the launch is aborting.
+__device__ inline void bar_wait(const Args& a, unsigned k, Ctl* cur, int* ok) {
+  if (kp_tid() == 0) {
+    unsigned long long* rw = release_word(a);
+    unsigned long long w = cload(rw);
+    int good = 1;
+    if ((unsigned)(w >> 32) < k) {
+      const int64_t t0 = wall_clock64();
+      for (unsigned it = 1;; ++it) {
+        w = cload(rw);
+        if ((unsigned)(w >> 32) >= k) break;
+        if ((it & 31u) == 0u && (aborted(a) || wait_expired(a, t0))) {
+          good = 0;
+          break;
+        }
+      }
+    }
+    *ok = good;
+    if (good) *cur = ctl_unpack((unsigned)w);
+  }
   __syncthreads();
 }
 
@@ -249,19 +329,24 @@ __device__ inline void bar_wait(const Args& a, unsigned k) {
 __device__ inline void flag_publish(const Args& a, unsigned k) {
   wait_all_stores();
   __syncthreads();
-  if (threadIdx.x == 0) cstore(a.flags + (int64_t)blockIdx.x * kFlagStride, k);
+  if (kp_tid() == 0) cstore(a.flags + (int64_t)blockIdx.x * kFlagStride, k);
 }
 
 // Wait until the two row neighbours (halo) and workgroup 0 (tail) have
-// published the vector of barrier k.
+// published the vector of barrier k (the three flags are polled together).
 __device__ inline void flag_wait_neighbours(const Args& a, unsigned k) {
-  if (threadIdx.x == 0) {
+  if (kp_tid() == 0) {
     const int b = (int)blockIdx.x, nw = a.nwg;
-    const int prev = (b == 0) ? nw - 1 : b - 1;
-    const int next = (b + 1 == nw) ? 0 : b + 1;
-    spin_until(a, a.flags + (int64_t)prev * kFlagStride, k);
-    spin_until(a, a.flags + (int64_t)next * kFlagStride, k);
-    spin_until(a, a.flags, k);
+    const unsigned* fp = a.flags + (int64_t)((b == 0) ? nw - 1 : b - 1) * kFlagStride;
+    const unsigned* fn = a.flags + (int64_t)((b + 1 == nw) ? 0 : b + 1) * kFlagStride;
+    const unsigned* f0 = a.flags;
+    int64_t t0 = 0;
+    for (unsigned it = 0;; ++it) {
+      const unsigned vp = cload(fp), vn = cload(fn), v0 = cload(f0);
+      if (vp >= k && vn >= k && v0 >= k) break;
+      if (it == 0) t0 = wall_clock64();
+      if ((it & 31u) == 31u && (aborted(a) || wait_expired(a, t0))) break;
+    }
   }
   __syncthreads();
 }

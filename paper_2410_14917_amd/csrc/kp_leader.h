@@ -17,9 +17,9 @@ namespace kp {
 // reduction costs about one memory latency per 64 workgroups.
 // grp: LDS scratch of kRg * kKStride doubles.
 constexpr int kRg = 4;
-__device__ inline void reduce_partials(const Args& a, int nslot, double* dst, double* grp) {
+__device__ __attribute__((always_inline)) inline void reduce_partials(const Args& a, int nslot, double* dst, double* grp) {
   constexpr int kS = kThreads / kRg;
-  const int g = threadIdx.x / kS, l = threadIdx.x % kS;
+  const int g = kp_tid() / kS, l = kp_tid() % kS;
   for (int kb = 0; kb < nslot; kb += kS) {
     const int k = kb + l;
     if (k < nslot) {
@@ -38,7 +38,7 @@ __device__ inline void reduce_partials(const Args& a, int nslot, double* dst, do
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nslot; k += kThreads) {
+  for (int k = kp_tid(); k < nslot; k += kThreads) {
     double s = 0.0;
 #pragma unroll
     for (int gg = 0; gg < kRg; ++gg) s += grp[gg * kKStride + k];
@@ -48,9 +48,9 @@ __device__ inline void reduce_partials(const Args& a, int nslot, double* dst, do
 }
 
 // ---- stage leader: balance mu, augmented tail, first phase -----------------
-__device__ inline void leader_stage(const Args& a, double* red) {
+__device__ __attribute__((always_inline)) inline void leader_stage(const Args& a, double* red, Ctl& nx) {
   double m0 = 0.0, m1 = 0.0;
-  for (int w = threadIdx.x; w < a.nwg; w += kThreads) {
+  for (int w = kp_tid(); w < a.nwg; w += kThreads) {
     m0 = fmax(m0, cload(a.part + (int64_t)w * kKStride + 0));
     m1 = fmax(m1, cload(a.part + (int64_t)w * kKStride + 1));
   }
@@ -62,25 +62,25 @@ __device__ inline void leader_stage(const Args& a, double* red) {
     frexp(mx, &e);
     mu = ldexp(1.0, e - 1);            // largest power of two <= max |b_k|
   }
-  for (int k = threadIdx.x; k < kTailPad; k += kThreads) {
+  for (int k = kp_tid(); k < kTailPad; k += kThreads) {
     const double v = (a.p > 0 && k == a.p - 1) ? mu : 0.0;
     a.u[a.tail_off + k] = v;
     cstore(a.tx + k, v);
   }
-  if (threadIdx.x == 0) {
+  if (kp_tid() == 0) {
     State* st = a.st;
     Pub* pb = a.pub;
     st->mu = mu;
     cstore(&pb->inv_mu, 1.0 / mu);
     if (bad != 0.0) {
-      cstore(&pb->status, (int)KP_STATUS_NONFINITE);
-      cstore(&pb->phase, (int)PH_FINISH);
+      nx.status = (int)KP_STATUS_NONFINITE;
+      nx.phase = (int)PH_FINISH;
     } else if (a.h == 0.0) {
-      cstore(&pb->phase, (int)PH_FINISH);
+      nx.phase = (int)PH_FINISH;
     } else {
-      cstore(&pb->j, 0);
-      cstore(&pb->upd, 0);
-      cstore(&pb->phase, (int)PH_STEP);
+      nx.j = 0;
+      nx.upd = 0;
+      nx.phase = (int)PH_STEP;
     }
   }
 }
@@ -99,12 +99,12 @@ __device__ inline void load_tables(const Args& a, double* tabs) {
   double* Mi = tabs;
   double* Li = tabs + kMMax * kTabLd;
   double* sg = tabs + 2 * kMMax * kTabLd;
-  for (int idx = threadIdx.x; idx < kMMax * kMMax; idx += kThreads) {
+  for (int idx = kp_tid(); idx < kMMax * kMMax; idx += kThreads) {
     const int k = idx / kMMax, r = idx - k * kMMax;
     Mi[k * kTabLd + r] = st->Minv[(int64_t)k * kLdt + r];
     Li[k * kTabLd + r] = st->Lm[(int64_t)k * kLdt + r];
   }
-  for (int i = threadIdx.x; i < kMMax; i += kThreads) sg[i] = st->sigma[i];
+  for (int i = kp_tid(); i < kMMax; i += kThreads) sg[i] = st->sigma[i];
   __syncthreads();
 }
 
@@ -119,7 +119,7 @@ constexpr int kWkDoubles = kWkPart + kWaves * 64;
 // K(i): 0 -> k <= i, 1 -> k < i, 2 -> i < k <= jj.
 template <int MODE, bool TR>
 __device__ inline double tri_mv(int jj, const double* tab, const double* v, double* part) {
-  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = kp_tid() & 63, g = kp_tid() >> 6;
   double acc = 0.0;
   if (i <= jj) {
     const int klo = (MODE == 2) ? i + 1 : 0;
@@ -130,7 +130,7 @@ __device__ inline double tri_mv(int jj, const double* tab, const double* v, doub
   part[g * 64 + i] = acc;
   __syncthreads();
   double s = 0.0;
-  if (threadIdx.x < 64) {
+  if (kp_tid() < 64) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += part[w * 64 + i];
   }
@@ -143,8 +143,8 @@ __device__ inline double tri_mv(int jj, const double* tab, const double* v, doub
 // vector the matvec multiplied, so alpha = ||x_j|| is the lagged true norm and
 // H_{j,j-1} = gamma_{j-1} alpha (gamma = divisor applied to x_j when written).
 // Every thread of the workgroup calls this; wave 0 holds row i = lane.
-__device__ inline void scalar_step(const Args& a, int jj, const double* tv, double* tabs,
-                                   double* wk) {
+__device__ __attribute__((always_inline)) inline void scalar_step(const Args& a, int jj, const double* tv, double* tabs,
+                                   double* wk, Ctl& nx) {
   State* st = a.st;
   Pub* pb = a.pub;
   double* Mi = tabs;
@@ -155,8 +155,8 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv, doub
   double* sy = wk + kWkY;
   double* sp = wk + kWkP;
   double* part = wk + kWkPart;
-  const int i = threadIdx.x;               // row index in wave 0
-  const bool w0 = threadIdx.x < 64;
+  const int i = kp_tid();               // row index in wave 0
+  const bool w0 = kp_tid() < 64;
   const double gj = tv[2 * jj], cj = tv[2 * jj + 1], cww = tv[2 * jj + 2];
   const double alpha = sqrt(gj);
   if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(cww)) {
@@ -164,16 +164,16 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv, doub
       if (jj == 0 && alpha == 0.0) {        // zero start vector: result is zero
         st->zero = 1;
         st->beta = 0.0;
-        cstore(&pb->phase, (int)PH_FINISH);
+        nx.phase = (int)PH_FINISH;
       } else if (alpha == 0.0) {            // exact invariance already reached
         st->breakdown = 1;
-        cstore(&pb->m_eff, jj);
-        cstore(&pb->upd, 0);
+        nx.m_eff = jj;
+        nx.upd = 0;
         st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
-        cstore(&pb->phase, (int)PH_EXPM);
+        nx.phase = (int)PH_EXPM;
       } else {
-        cstore(&pb->status, (int)KP_STATUS_NONFINITE);
-        cstore(&pb->phase, (int)PH_FINISH);
+        nx.status = (int)KP_STATUS_NONFINITE;
+        nx.phase = (int)PH_FINISH;
       }
     }
     return;
@@ -184,10 +184,10 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv, doub
     if (i == 0) {
       st->breakdown = 1;
       st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
-      cstore(&pb->j, jj);
-      cstore(&pb->m_eff, jj);
-      cstore(&pb->upd, 0);
-      cstore(&pb->phase, (int)PH_EXPM);
+      nx.j = jj;
+      nx.m_eff = jj;
+      nx.upd = 0;
+      nx.phase = (int)PH_EXPM;
     }
     return;
   }
@@ -265,23 +265,23 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv, doub
     st->fallback_cur = fallback;
     st->n_fallback += fallback;
     if (bad) {
-      cstore(&pb->status, (int)KP_STATUS_NONFINITE);
-      cstore(&pb->phase, (int)PH_FINISH);
+      nx.status = (int)KP_STATUS_NONFINITE;
+      nx.phase = (int)PH_FINISH;
     } else if (bd) {
       st->H[(int64_t)jj * kLdh + jj + 1] = 0.0;
       st->breakdown = 1;
       st->arnoldi_steps += 1;
-      cstore(&pb->j, jj + 1);
-      cstore(&pb->m_eff, jj + 1);
-      cstore(&pb->upd, 0);
-      cstore(&pb->phase, (int)PH_EXPM);
+      nx.j = jj + 1;
+      nx.m_eff = jj + 1;
+      nx.upd = 0;
+      nx.phase = (int)PH_EXPM;
     } else {
       const int j = jj + 1;
       st->arnoldi_steps += 1;
-      cstore(&pb->j, j);
-      cstore(&pb->m_eff, j);
-      cstore(&pb->upd, 1);
-      cstore(&pb->phase, (int)((j >= st->m_target || j >= a.stop_j) ? PH_CLOSE : PH_STEP));
+      nx.j = j;
+      nx.m_eff = j;
+      nx.upd = 1;
+      nx.phase = (int)((j >= st->m_target || j >= a.stop_j) ? PH_CLOSE : PH_STEP);
     }
   }
 }
@@ -290,25 +290,24 @@ __device__ inline void scalar_step(const Args& a, int jj, const double* tv, doub
 // After the pending update produced x_j (j = completed steps), its exact norm
 // gives the last subdiagonal H_{j+1,j} = gamma_{j-1} ||x_j|| (the final
 // reduction of Algorithm 4).
-__device__ inline void leader_close(const Args& a, double nrm2) {
-  if (threadIdx.x != 0) return;
+__device__ __attribute__((always_inline)) inline void leader_close(const Args& a, double nrm2, Ctl& nx) {
+  if (kp_tid() != 0) return;
   State* st = a.st;
-  Pub* pb = a.pub;
-  const int j = cload(&pb->j);
+  const int j = nx.j;
   const double nrm = sqrt(nrm2);
   st->H[(int64_t)(j - 1) * kLdh + j] = st->gamma[j - 1] * nrm;
   st->last_nrm2 = nrm2;
-  cstore(&pb->upd, 0);
+  nx.upd = 0;
   if (!isfinite(nrm2)) {
-    cstore(&pb->status, (int)KP_STATUS_NONFINITE);
-    cstore(&pb->phase, (int)PH_FINISH);
+    nx.status = (int)KP_STATUS_NONFINITE;
+    nx.phase = (int)PH_FINISH;
     return;
   }
   if (st->fallback_cur && nrm <= a.eps_bd * sqrt(st->wn2[j - 1])) {
     st->H[(int64_t)(j - 1) * kLdh + j] = 0.0;
     st->breakdown = 1;
   }
-  cstore(&pb->phase, (int)((st->breakdown || j >= st->m_target) ? PH_EXPM : PH_STEP));
+  nx.phase = (int)((st->breakdown || j >= st->m_target) ? PH_EXPM : PH_STEP);
 }
 
 // ---- small exponential + substep controller (workgroup 0) -------------------
@@ -325,13 +324,13 @@ __device__ inline double tau_factor(double omega, int m) {
   return fmin(4.0, fmax(0.2, 0.9 * pow(omega, -1.0 / (double)(q + 1))));
 }
 
-__device__ inline void expm_phase(const Args& a, double* lds) {
+__device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, double* lds, Ctl& nx) {
   __shared__ int s_dec;
   __shared__ double s_tau;
   State* st = a.st;
   Pub* pb = a.pub;
   const bool fixed = a.fixed_m > 0;
-  const int m = cload(&pb->m_eff);
+  const int m = nx.m_eff;
   const bool happy = st->breakdown != 0;
   const double t = st->t, beta = st->beta;
   double tau = st->tau;
@@ -339,7 +338,7 @@ __device__ inline void expm_phase(const Args& a, double* lds) {
   int dec = D_ACCEPT;
   while (true) {
     expm_hbar(a, st->H, kLdh, m, tau, happy, st->F, lds);
-    if (threadIdx.x == 0) {
+    if (kp_tid() == 0) {
       st->expm_evals += 1;
       const double err = happy ? 0.0 : beta * fabs(st->F[m]);
       double omega = 0.0;
@@ -370,39 +369,37 @@ __device__ inline void expm_phase(const Args& a, double* lds) {
     if (dec != D_SHRINK) break;
   }
   if (dec == D_ACCEPT) {
-    for (int i = threadIdx.x; i < m; i += kThreads)
+    for (int i = kp_tid(); i < m; i += kThreads)
       cstore(&pb->coef[i], beta * st->F[i] * st->sigma[i]);
-    if (threadIdx.x == 0) {
+    if (kp_tid() == 0) {
       st->tau = tau;
       const int last = fixed ? (st->substeps + 1 >= a.fixed_substeps) : (tau >= a.h - t);
-      cstore(&pb->last, last);
-      cstore(&pb->phase, (int)PH_COMBINE);
+      nx.last = last;
+      nx.phase = (int)PH_COMBINE;
     }
   } else if (dec == D_GROW) {
-    if (threadIdx.x == 0) {
+    if (kp_tid() == 0) {
       st->m_cur = min(2 * st->m_cur, a.m_max);
       st->m_target = st->m_cur;
       st->tau = tau;
-      cstore(&pb->upd, 0);
-      cstore(&pb->phase, (int)PH_STEP);
+      nx.upd = 0;
+      nx.phase = (int)PH_STEP;
     }
   } else {
-    if (threadIdx.x == 0) {
-      cstore(&pb->status,
-             (int)((dec == D_FAIL_NF) ? KP_STATUS_NONFINITE : KP_STATUS_NOT_CONVERGED));
-      cstore(&pb->phase, (int)PH_FINISH);
+    if (kp_tid() == 0) {
+      nx.status = (int)((dec == D_FAIL_NF) ? KP_STATUS_NONFINITE : KP_STATUS_NOT_CONVERGED);
+      nx.phase = (int)PH_FINISH;
     }
   }
   __syncthreads();
 }
 
 // ---- after the combine: advance time, next substep -------------------------
-__device__ inline void leader_combine(const Args& a) {
-  if (threadIdx.x != 0) return;
+__device__ __attribute__((always_inline)) inline void leader_combine(const Args& a, Ctl& nx) {
+  if (kp_tid() != 0) return;
   State* st = a.st;
-  Pub* pb = a.pub;
   const bool fixed = a.fixed_m > 0;
-  const int m = cload(&pb->m_eff);
+  const int m = nx.m_eff;
   const double tau = st->tau;
   if (st->nlog < kLogMax) {
     st->log_tau[st->nlog] = tau;
@@ -412,19 +409,19 @@ __device__ inline void leader_combine(const Args& a) {
   st->err_max = fmax(st->err_max, st->err);
   st->substeps += 1;
   st->m_last = m;
-  const bool last = cload(&pb->last) != 0;
+  const bool last = nx.last != 0;
   st->t = last ? a.h : st->t + tau;
   if (st->breakdown) st->breakdowns += 1;
   if (last) {
-    cstore(&pb->phase, (int)PH_DONE);
+    nx.phase = (int)PH_DONE;
     return;
   }
   double tn = tau;
   if (!fixed) {
     tn = tau * tau_factor(st->omega, m);
     if (st->substeps >= a.max_substeps) {
-      cstore(&pb->status, (int)KP_STATUS_NOT_CONVERGED);
-      cstore(&pb->phase, (int)PH_FINISH);
+      nx.status = (int)KP_STATUS_NOT_CONVERGED;
+      nx.phase = (int)PH_FINISH;
       return;
     }
     tn = fmin(tn, a.h - st->t);
@@ -432,9 +429,9 @@ __device__ inline void leader_combine(const Args& a) {
   st->tau = tn;
   st->breakdown = 0;
   st->m_target = fixed ? a.fixed_m : st->m_cur;
-  cstore(&pb->j, 0);
-  cstore(&pb->upd, 0);
-  cstore(&pb->phase, (int)PH_STEP);
+  nx.j = 0;
+  nx.upd = 0;
+  nx.phase = (int)PH_STEP;
 }
 
 }  // namespace kp

@@ -45,6 +45,33 @@ template <> struct Pair<float> {
 
 template <typename TB> __device__ inline double rnd(double v) { return (double)(TB)v; }
 
+// A wave-uniform pointer, kept in scalar registers: column accesses are then a
+// scalar base plus a 32-bit per-lane byte offset, and the compiler cannot
+// re-associate the base into per-lane 64-bit loop invariants.
+template <typename T>
+__device__ inline T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+#define KP_GLOBAL __attribute__((address_space(1)))
+typedef double kp_d2 __attribute__((ext_vector_type(2)));
+typedef float kp_f2 __attribute__((ext_vector_type(2)));
+
+template <typename TB>
+__device__ inline double2 load_at(const TB* base, uint32_t byte_off) {
+  const KP_GLOBAL char* p = (const KP_GLOBAL char*)base + byte_off;
+  if constexpr (sizeof(TB) == 8) {
+    const kp_d2 v = *(const KP_GLOBAL kp_d2*)p;
+    return make_double2(v.x, v.y);
+  } else {
+    const kp_f2 v = *(const KP_GLOBAL kp_f2*)p;
+    return make_double2((double)v.x, (double)v.y);
+  }
+}
+
 // Vector multiplied by the matvec of step jj: the float64 state u at the first
 // step (rounded through the basis type, which is what basis column 0 stores),
 // the stored basis column afterwards.  Own elements only (plain loads).
@@ -95,34 +122,41 @@ __device__ inline Seg seg_at(const Args& a, const Rows& o, int si) {
   return Seg{a.tail_off, a.tail_off + kTailPad, 0, true};
 }
 
+// Index of the halo slot of (workgroup w, plane s, side: 0 first row, 1 last row).
+__device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix) {
+  return ((int64_t)(w * a.nplanes + s) * 2 + side) * a.nx + ix;
+}
+
 constexpr int kR = 4;    // element pairs per thread per sub-tile
-constexpr int kCh = 4;   // basis columns per chunk of the inner-product loop
+constexpr int kCh = 2;   // basis columns per chunk of the inner-product loop
 constexpr int kCu = 8;   // basis columns per chunk of the linear combinations
 
-// Pair indices of this lane in the sub-tile starting at pair q0; pairs past
-// pend are clamped to the last pair (ok = false).
-__device__ inline void tile_pairs(int64_t q0, int64_t pend, int64_t* qc, bool* ok) {
+// Element offsets of this lane's kR pairs in the sub-tile that starts at
+// element 2*q0 (lane offsets stay below 2 * kThreads * kR, so every column
+// access is a uniform base plus a 32-bit lane offset); pairs past pend are
+// clamped to the last pair (ok = false).
+__device__ inline void tile_pairs(int64_t q0, int64_t pend, uint32_t* lo, bool* ok) {
 #pragma unroll
   for (int r = 0; r < kR; ++r) {
-    const int64_t q = q0 + (int64_t)r * kThreads + threadIdx.x;
+    const int64_t q = q0 + (int64_t)r * kThreads + kp_tid();
     ok[r] = q < pend;
-    qc[r] = ok[r] ? q : pend - 1;
+    lo[r] = (uint32_t)(2 * ((ok[r] ? q : pend - 1) - q0));
   }
 }
 
-// acc[r] += sum over the C columns i = i0, i0 + step, ... of coef[i] V_i(pair qc[r]).
+// acc[r] += sum over the C columns i = i0, i0 + step, ... of coef[i] V_i(pair r).
 // All C * kR loads are issued before the first multiply-add.
 template <typename TB, int C>
-__device__ inline void axpy_cols(const TB* V, int64_t ld, int i0, int step, const double* coef,
-                                 const int64_t* qc, double2* acc) {
+__device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, int step,
+                                 const double* coef, const uint32_t* lo, double2* acc) {
   double2 v[C][kR];
   double ci[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const TB* vc = V + (int64_t)(i0 + c * step) * ld;
+    const TB* vc = uniform_ptr(V + (int64_t)(i0 + c * step) * ld + t0);
     ci[c] = coef[i0 + c * step];
 #pragma unroll
-    for (int r = 0; r < kR; ++r) v[c][r] = Pair<TB>::load(vc + 2 * qc[r]);
+    for (int r = 0; r < kR; ++r) v[c][r] = load_at(vc, lo[r] * (uint32_t)sizeof(TB));
   }
 #pragma unroll
   for (int c = 0; c < C; ++c)
@@ -133,29 +167,28 @@ __device__ inline void axpy_cols(const TB* V, int64_t ld, int i0, int step, cons
     }
 }
 
-// Index of the halo slot of (workgroup w, plane s, side: 0 first row, 1 last row).
-__device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix) {
-  return ((int64_t)(w * a.nplanes + s) * 2 + side) * a.nx + ix;
+// A producer of a vector that the next matvec multiplies publishes, with
+// coherent stores, the elements of the first and last row of each owned plane
+// segment (the stencil halo of the neighbouring workgroups) and the tail
+// (workgroup 0).  Called for the element pair (e, e+1) of segment sg with the
+// values as stored; lanes outside the boundary rows store nothing.
+__device__ inline void publish_elem(const Args& a, const Seg& sg, int64_t e, double v) {
+  if (e >= sg.end) return;
+  if (sg.tail) {
+    cstore(a.tx + (e - a.tail_off), v);
+    return;
+  }
+  const int64_t off = e - sg.beg, last0 = sg.end - sg.beg - a.nx;
+  if (off < a.nx) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 0, (int)off), v);
+  if (off >= last0) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 1, (int)(off - last0)), v);
 }
 
-// After a pass produced vector x (own elements, plain stores), publish the
-// first and last row of the owned range of every plane (stencil halo of the
-// neighbouring workgroups) and, for workgroup 0, the augmented tail, with
-// coherent stores.  Reads back this workgroup's own fresh data.
-template <typename T>
-__device__ inline void publish_halo(const Args& a, const Rows& o, const T* x) {
-  __syncthreads();
-  const int nx = a.nx;
-  for (int s = 0; s < a.nplanes; ++s) {
-    const int64_t base = (int64_t)s * a.npt_pad;
-    for (int ix = threadIdx.x; ix < nx; ix += kThreads) {
-      cstore(a.hx + halo_at(a, blockIdx.x, s, 0, ix), (double)x[base + (int64_t)o.r0 * nx + ix]);
-      cstore(a.hx + halo_at(a, blockIdx.x, s, 1, ix),
-             (double)x[base + (int64_t)(o.r1 - 1) * nx + ix]);
-    }
+__device__ inline void publish_pair(const Args& a, const Seg& sg, int64_t e, double v0,
+                                    double v1) {
+  if (sg.tail || e - sg.beg < a.nx || e + 1 >= sg.end - a.nx) {
+    publish_elem(a, sg, e, v0);
+    publish_elem(a, sg, e + 1, v1);
   }
-  if (blockIdx.x == 0)
-    for (int k = threadIdx.x; k < kTailPad; k += kThreads) cstore(a.tx + k, (double)x[a.tail_off + k]);
 }
 
 // Copy the halo rows this workgroup's stencil needs (the first row of the next
@@ -167,7 +200,7 @@ __device__ inline void stage_halo(const Args& a, const Rows& o, double* hl) {
   const int wn = (o.r1 == a.ny) ? 0 : b + 1;
   const int ws = (o.r0 == 0) ? a.nwg - 1 : b - 1;
   for (int s = 0; s < a.nplanes; ++s)
-    for (int ix = threadIdx.x; ix < nx; ix += kThreads) {
+    for (int ix = kp_tid(); ix < nx; ix += kThreads) {
       hl[s * nx + ix] = rnd<TB>(cload(a.hx + halo_at(a, wn, s, 0, ix)));
       hl[(a.nplanes + s) * nx + ix] = rnd<TB>(cload(a.hx + halo_at(a, ws, s, 1, ix)));
     }
@@ -237,12 +270,12 @@ __device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x,
 // the padding.
 template <typename TB, bool HL>
 __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, const Src<TB>& x,
-                                const double* hl, const int64_t* qc, const double* tc,
-                                double2* w) {
+                                const double* hl, int64_t t0, const uint32_t* lo,
+                                const double* tc, double2* w) {
   if (sg.tail) {
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-      const int64_t e = 2 * qc[r];
+      const int64_t e = t0 + lo[r];
       const int64_t k = e - a.tail_off;
       const double2 nx2 = x.pair(e + 2 < sg.end ? e + 2 : e);
       const double v1 = x(e + 1);
@@ -255,37 +288,53 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
   const int64_t xoff = (int64_t)sg.plane * a.npt;   // external plane offset
 #pragma unroll
   for (int r = 0; r < kR; ++r) {
-    const int64_t e = 2 * qc[r];
+    const int64_t e = t0 + lo[r];
     const bool v1 = e + 1 < sg.end;
     const int q = (int)(e - base);
     w[r].x = op_elem<TB, HL>(a, o, x, hl, sg.plane, e, q, true);
     const double y = op_elem<TB, HL>(a, o, x, hl, sg.plane, v1 ? e + 1 : e, v1 ? q + 1 : q, v1);
     w[r].y = v1 ? y : 0.0;
   }
-  for (int c = 0; c < a.p; ++c) {
-    const int64_t col = (int64_t)(a.p - c) * a.ldb + xoff - base;
-    const double t = tc[c];
+  // B-hat x_tail / mu: the columns b_{p-c}, two at a time with all their
+  // loads issued before the first use
+  for (int c0 = 0; c0 < a.p; c0 += 2) {
+    double bv[2][kR][2];
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      const int64_t e = 2 * qc[r];
-      const bool v1 = e + 1 < sg.end;
-      const double b0 = a.B[col + e];
-      const double b1 = a.B[col + (v1 ? e + 1 : e)];
-      w[r].x += t * b0;
-      w[r].y += v1 ? t * b1 : 0.0;
+    for (int c = 0; c < 2; ++c) {
+      if (c0 + c < a.p) {
+        const int64_t col = (int64_t)(a.p - c0 - c) * a.ldb + xoff - base;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const int64_t e = t0 + lo[r];
+          bv[c][r][0] = a.B[col + e];
+          bv[c][r][1] = a.B[col + ((e + 1 < sg.end) ? e + 1 : e)];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c0 + c < a.p) {
+        const double t = tc[c0 + c];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const bool v1 = t0 + lo[r] + 1 < sg.end;
+          w[r].x += t * bv[c][r][0];
+          w[r].y += v1 ? t * bv[c][r][1] : 0.0;
+        }
+      }
     }
   }
 }
 
 // ---- stage: u = [b_0; 0] (the leader adds mu e_p), max |b_k| for k >= 1 -----
 // Partial slots: [0] = max |b_k|, [1] = 1 if a non-finite entry was seen.
-__device__ inline void stage_pass(const Args& a, double* red) {
+__device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, double* red) {
   const Rows o = own_rows(a);
   double mx = 0.0, bad = 0.0;
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
-    for (int64_t e = sg.beg + threadIdx.x; e < ((sg.end + 1) & ~(int64_t)1); e += kThreads) {
+    for (int64_t e = sg.beg + kp_tid(); e < ((sg.end + 1) & ~(int64_t)1); e += kThreads) {
       double v = 0.0;
       if (!sg.tail && e < sg.end) {
         const int64_t eext = e - (int64_t)sg.plane * a.npt_pad + (int64_t)sg.plane * a.npt;
@@ -298,12 +347,12 @@ __device__ inline void stage_pass(const Args& a, double* red) {
         }
       }
       a.u[e] = v;
+      if (!sg.tail) publish_elem(a, sg, e, v);   // the tail is completed by the leader
     }
   }
-  publish_halo(a, o, a.u);     // the tail is completed by the leader
   mx = block_max(mx, red);
   bad = block_max(bad, red);
-  if (threadIdx.x == 0) {
+  if (kp_tid() == 0) {
     cstore(a.part + (int64_t)blockIdx.x * kKStride + 0, mx);
     cstore(a.part + (int64_t)blockIdx.x * kKStride + 1, bad);
   }
@@ -315,42 +364,84 @@ __device__ inline void stage_pass(const Args& a, double* red) {
 // inner products of V_{1:j+1}^T [x_j, w] (eq. output_wywnrm):
 //   slot 2i = x_i . x,  slot 2i+1 = x_i . w  (i <= jj),  slot 2jj+2 = w . w.
 // sacc: kWaves * kKStride doubles of LDS; hl: the LDS halo copy (HL).
+//
+// The older columns are visited kCh at a time, software-pipelined: the loads
+// of the next chunk are in flight while the wave reduces the current one.
+
+// Per-wave sums of x_i . x and x_i . w for the kCh columns of one chunk
+// (columns past nc repeat the last one and are not recorded).
+template <int C>
+__device__ inline void dots_chunk(const double2 (&v)[C][kR], const double2* xv,
+                                  const double2* wv2, int i0, int nc, double* sacc) {
+  const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double ax = 0.0, aw = 0.0;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      ax += v[c][r].x * xv[r].x + v[c][r].y * xv[r].y;
+      aw += v[c][r].x * wv2[r].x + v[c][r].y * wv2[r].y;
+    }
+    if (c < nc) {
+      ax = wave_sum(ax);
+      aw = wave_sum(aw);
+      if (lane == 0) {
+        sacc[wv * kKStride + 2 * (i0 + c)] += ax;
+        sacc[wv * kKStride + 2 * (i0 + c) + 1] += aw;
+      }
+    }
+  }
+}
+
+template <typename TB, int C>
+__device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, int nc,
+                                  const uint32_t* lo, double2 (&v)[C][kR]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const TB* vc = uniform_ptr(V + (int64_t)(i0 + min(c, nc - 1)) * ld + t0);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) v[c][r] = load_at(vc, lo[r] * (uint32_t)sizeof(TB));
+  }
+}
+
 template <typename TB, bool HL>
-__device__ inline void matvec_dots_pass(const Args& a, int jj, double inv_mu, double* sacc,
-                                        double* hl) {
+__device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Args& a, int jj, double* sacc, double* hl) {
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
   const Rows o = own_rows(a);
-  for (int k = threadIdx.x; k < kWaves * kKStride; k += kThreads) sacc[k] = 0.0;
+  for (int k = kp_tid(); k < kWaves * kKStride; k += kThreads) sacc[k] = 0.0;
   if (HL) stage_halo<TB>(a, o, hl);
+  const double inv_mu = cload(&a.pub->inv_mu);
+  double tc[kPMax];
+#pragma unroll
+  for (int c = 0; c < kPMax; ++c) tc[c] = (c < a.p) ? rnd<TB>(cload(a.tx + c)) * inv_mu : 0.0;
   __syncthreads();
   TB* xcol = V + (int64_t)jj * ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
   const Src<TB> x{xcol, a.u, jj == 0};
-  double tc[kPMax];
-#pragma unroll
-  for (int c = 0; c < kPMax; ++c) tc[c] = (c < a.p) ? rnd<TB>(cload(a.tx + c)) * inv_mu : 0.0;
   double sxx = 0.0, sxw = 0.0, sww = 0.0;
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
     const int64_t pend = (sg.end + 1) >> 1;
     for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
-      int64_t qc[kR];
+      const int64_t t0 = 2 * q0;
+      uint32_t lo[kR];
       bool ok[kR];
-      tile_pairs(q0, pend, qc, ok);
+      tile_pairs(q0, pend, lo, ok);
       double2 xv[kR], wv2[kR];
+      double2 va[kCh][kR], vb[kCh][kR];
 #pragma unroll
-      for (int r = 0; r < kR; ++r) xv[r] = x.pair(2 * qc[r]);
-      aug_tile<TB, HL>(a, o, sg, x, hl, qc, tc, wv2);
+      for (int r = 0; r < kR; ++r) xv[r] = x.pair(t0 + lo[r]);
+      aug_tile<TB, HL>(a, o, sg, x, hl, t0, lo, tc, wv2);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         wv2[r].x = rnd<TB>(wv2[r].x);
         wv2[r].y = rnd<TB>(wv2[r].y);
         if (ok[r]) {
-          Pair<TB>::store(wcol + 2 * qc[r], wv2[r].x, wv2[r].y);
-          if (jj == 0) Pair<TB>::store(xcol + 2 * qc[r], xv[r].x, xv[r].y);
+          Pair<TB>::store(wcol + t0 + lo[r], wv2[r].x, wv2[r].y);
+          if (jj == 0) Pair<TB>::store(xcol + t0 + lo[r], xv[r].x, xv[r].y);
         } else {
           xv[r] = make_double2(0.0, 0.0);
           wv2[r] = make_double2(0.0, 0.0);
@@ -362,34 +453,16 @@ __device__ inline void matvec_dots_pass(const Args& a, int jj, double inv_mu, do
         sxw += xv[r].x * wv2[r].x + xv[r].y * wv2[r].y;
         sww += wv2[r].x * wv2[r].x + wv2[r].y * wv2[r].y;
       }
-      // x_i . x and x_i . w for the older columns, kCh columns at a time
-      int i0 = 0;
-      for (; i0 < jj; i0 += kCh) {
-        const int nc = min(kCh, jj - i0);
-        double2 v[kCh][kR];
-#pragma unroll
-        for (int c = 0; c < kCh; ++c) {
-          const TB* vc = V + (int64_t)(i0 + min(c, nc - 1)) * ld;
-#pragma unroll
-          for (int r = 0; r < kR; ++r) v[c][r] = Pair<TB>::load(vc + 2 * qc[r]);
-        }
-#pragma unroll
-        for (int c = 0; c < kCh; ++c) {
-          double ax = 0.0, aw = 0.0;
-#pragma unroll
-          for (int r = 0; r < kR; ++r) {
-            ax += v[c][r].x * xv[r].x + v[c][r].y * xv[r].y;
-            aw += v[c][r].x * wv2[r].x + v[c][r].y * wv2[r].y;
-          }
-          if (c < nc) {
-            ax = wave_sum(ax);
-            aw = wave_sum(aw);
-            if (lane == 0) {
-              sacc[wv * kKStride + 2 * (i0 + c)] += ax;
-              sacc[wv * kKStride + 2 * (i0 + c) + 1] += aw;
-            }
-          }
-        }
+      // x_i . x and x_i . w for the older columns, two chunks in flight
+      if (jj > 0) load_chunk<TB, kCh>(V, ld, t0, 0, min(kCh, jj), lo, va);
+      for (int i0 = 0; i0 < jj; i0 += 2 * kCh) {
+        const int i1 = i0 + kCh;
+        if (i1 < jj) load_chunk<TB, kCh>(V, ld, t0, i1, min(kCh, jj - i1), lo, vb);
+        dots_chunk<kCh>(va, xv, wv2, i0, min(kCh, jj - i0), sacc);
+        if (i1 >= jj) break;
+        const int i2 = i1 + kCh;
+        if (i2 < jj) load_chunk<TB, kCh>(V, ld, t0, i2, min(kCh, jj - i2), lo, va);
+        dots_chunk<kCh>(vb, xv, wv2, i1, min(kCh, jj - i1), sacc);
       }
     }
   }
@@ -403,7 +476,7 @@ __device__ inline void matvec_dots_pass(const Args& a, int jj, double inv_mu, do
   }
   __syncthreads();
   const int nslot = 2 * jj + 3;
-  for (int k = threadIdx.x; k < nslot; k += kThreads) {
+  for (int k = kp_tid(); k < nslot; k += kThreads) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += sacc[w * kKStride + k];
     cstore(a.part + (int64_t)blockIdx.x * kKStride + k, s);
@@ -417,7 +490,7 @@ __device__ inline void matvec_dots_pass(const Args& a, int jj, double inv_mu, do
 // only when the Arnoldi process closes).  Columns are visited from the newest
 // to the oldest, so the ones the previous matvec pass read last come first.
 template <typename TB>
-__device__ inline void update_pass(const Args& a, int jj, const double* coef, double* red,
+__device__ __attribute__((always_inline)) inline void update_pass(const Args& a, int jj, const double* coef, double* red,
                                    bool want_norm) {
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
@@ -430,39 +503,40 @@ __device__ inline void update_pass(const Args& a, int jj, const double* coef, do
     const Seg sg = seg_at(a, o, si);
     const int64_t pend = (sg.end + 1) >> 1;
     for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
-      int64_t qc[kR];
+      const int64_t t0 = 2 * q0;
+      uint32_t lo[kR];
       bool ok[kR];
-      tile_pairs(q0, pend, qc, ok);
+      tile_pairs(q0, pend, lo, ok);
       double2 acc[kR];
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
-        const double2 w = Pair<TB>::load(wcol + 2 * qc[r]);
+        const double2 w = Pair<TB>::load(wcol + t0 + lo[r]);
         acc[r] = make_double2(cw * w.x, cw * w.y);
       }
       int i1 = jj;
-      for (; i1 >= kCu - 1; i1 -= kCu) axpy_cols<TB, kCu>(V, ld, i1, -1, coef, qc, acc);
-      for (; i1 >= 0; --i1) axpy_cols<TB, 1>(V, ld, i1, -1, coef, qc, acc);
+      for (; i1 >= kCu - 1; i1 -= kCu) axpy_cols<TB, kCu>(V, ld, t0, i1, -1, coef, lo, acc);
+      for (; i1 >= 0; --i1) axpy_cols<TB, 1>(V, ld, t0, i1, -1, coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
         if (ok[r]) {
-          Pair<TB>::store(wcol + 2 * qc[r], y0, y1);
+          Pair<TB>::store(wcol + t0 + lo[r], y0, y1);
           ss += y0 * y0 + y1 * y1;
+          publish_pair(a, sg, t0 + lo[r], y0, y1);
         }
       }
     }
   }
-  publish_halo(a, o, wcol);
   if (want_norm) {
     ss = block_sum(ss, red);
-    if (threadIdx.x == 0) cstore(a.part + (int64_t)blockIdx.x * kKStride, ss);
+    if (kp_tid() == 0) cstore(a.part + (int64_t)blockIdx.x * kKStride, ss);
   }
 }
 
 // ---- combine: u = sum_{i<m} coef[i] x_i  (= beta V_m F, eq. kryexp) ----------
 // Also writes out = u_top when this is the last substep.
 template <typename TB>
-__device__ inline void combine_pass(const Args& a, int m, const double* coef, bool last) {
+__device__ __attribute__((always_inline)) inline void combine_pass(const Args& a, int m, const double* coef, bool last) {
   const TB* V = reinterpret_cast<const TB*>(a.V);
   const int64_t ld = a.ld;
   const Rows o = own_rows(a);
@@ -472,20 +546,22 @@ __device__ inline void combine_pass(const Args& a, int m, const double* coef, bo
     const int64_t pend = (sg.end + 1) >> 1;
     const int64_t shift = (int64_t)sg.plane * (a.npt - a.npt_pad);
     for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
-      int64_t qc[kR];
+      const int64_t t0 = 2 * q0;
+      uint32_t lo[kR];
       bool ok[kR];
-      tile_pairs(q0, pend, qc, ok);
+      tile_pairs(q0, pend, lo, ok);
       double2 acc[kR];
 #pragma unroll
       for (int r = 0; r < kR; ++r) acc[r] = make_double2(0.0, 0.0);
       int i0 = 0;
-      for (; i0 + kCu <= m; i0 += kCu) axpy_cols<TB, kCu>(V, ld, i0, 1, coef, qc, acc);
-      for (; i0 < m; ++i0) axpy_cols<TB, 1>(V, ld, i0, 1, coef, qc, acc);
+      for (; i0 + kCu <= m; i0 += kCu) axpy_cols<TB, kCu>(V, ld, t0, i0, 1, coef, lo, acc);
+      for (; i0 < m; ++i0) axpy_cols<TB, 1>(V, ld, t0, i0, 1, coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         if (ok[r]) {
-          const int64_t e = 2 * qc[r];
+          const int64_t e = t0 + lo[r];
           *reinterpret_cast<double2*>(a.u + e) = acc[r];
+          if (!last) publish_pair(a, sg, e, acc[r].x, acc[r].y);
           if (last && !sg.tail) {
             if (e < sg.end) a.out[e + shift] = acc[r].x;
             if (e + 1 < sg.end) a.out[e + 1 + shift] = acc[r].y;
@@ -494,16 +570,15 @@ __device__ inline void combine_pass(const Args& a, int m, const double* coef, bo
       }
     }
   }
-  if (!last) publish_halo(a, o, a.u);
 }
 
 // ---- finish: out = u_top (or NaN when the input was not finite) -------------
-__device__ inline void finish_pass(const Args& a, bool nonfinite) {
+__device__ __attribute__((always_inline)) inline void finish_pass(const Args& a, bool nonfinite) {
   const Rows o = own_rows(a);
   for (int si = 0; si < a.nplanes; ++si) {
     const Seg sg = seg_at(a, o, si);
     const int64_t shift = (int64_t)sg.plane * (a.npt - a.npt_pad);
-    for (int64_t e = sg.beg + threadIdx.x; e < sg.end; e += kThreads)
+    for (int64_t e = sg.beg + kp_tid(); e < sg.end; e += kThreads)
       a.out[e + shift] = nonfinite ? __builtin_nan("") : a.u[e];
   }
 }

@@ -45,29 +45,13 @@ static_assert(kOffGrp + kRg * kKStride <= kOffCoef, "grp overlaps coef");
 static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
 static_assert(kOffTv + kKStride <= kOffHl, "tv overlaps the halo copy");
 
-struct Ctrl {
-  int phase, j, upd, m_eff, last, status, abort_;
-  double inv_mu;
-};
-
-__device__ inline void read_ctrl(const Args& a, Ctrl* c) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const Pub* pb = a.pub;
-    c->phase = cload(&pb->phase);
-    c->j = cload(&pb->j);
-    c->upd = cload(&pb->upd);
-    c->m_eff = cload(&pb->m_eff);
-    c->last = cload(&pb->last);
-    c->status = cload(&pb->status);
-    c->inv_mu = cload(&pb->inv_mu);
-    c->abort_ = (int)cload(a.sync + 2);
-  }
-  __syncthreads();
-}
-
+// One phase of the call for this workgroup.  cur: control of the phase (LDS,
+// identical in every workgroup); nxt: the leader's control of the next phase;
+// ok: cleared when a bounded wait gives up (the launch is aborting).  On
+// return cur holds the control of the next phase.
 template <typename TB>
-__device__ void run_phase(const Args& a, double* lds, double* tabs, const Ctrl& c, unsigned k) {
+__device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, double* tabs, Ctl& cur, Ctl& nxt, int& ok,
+                          unsigned k) {
   double* sacc = lds + kOffSacc;
   double* grp = lds + kOffGrp;
   double* wk = lds + kOffWk;
@@ -76,93 +60,78 @@ __device__ void run_phase(const Args& a, double* lds, double* tabs, const Ctrl& 
   double* tv = lds + kOffTv;
   double* hl = lds + kOffHl;
   const bool lead = blockIdx.x == 0;
+  const Ctl c = cur;
+  // streaming part of the phase (every workgroup)
   switch (c.phase) {
     case PH_STAGE:
       stage_pass(a, red);
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        leader_stage(a, red);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
       break;
     case PH_STEP:
       // the update that produces x_j (coefficients of the previous scalar
       // step), then the matvec + grouped dots of step j: one grid-wide sync
       if (c.upd) {
-        for (int i = threadIdx.x; i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
+        for (int i = kp_tid(); i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
         __syncthreads();
         update_pass<TB>(a, c.j - 1, coef, red, false);
         flag_publish(a, k);
         flag_wait_neighbours(a, k);
       }
       if (a.halo_lds)
-        matvec_dots_pass<TB, true>(a, c.j, c.inv_mu, sacc, hl);
+        matvec_dots_pass<TB, true>(a, c.j, sacc, hl);
       else
-        matvec_dots_pass<TB, false>(a, c.j, c.inv_mu, sacc, hl);
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        reduce_partials(a, 2 * c.j + 3, tv, grp);
-        scalar_step(a, c.j, tv, tabs, wk);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
+        matvec_dots_pass<TB, false>(a, c.j, sacc, hl);
       break;
     case PH_CLOSE:
-      for (int i = threadIdx.x; i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
+      for (int i = kp_tid(); i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
       __syncthreads();
       update_pass<TB>(a, c.j - 1, coef, red, true);
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        reduce_partials(a, 1, tv, grp);
-        leader_close(a, tv[0]);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
-      break;
-    case PH_EXPM:
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        expm_phase(a, lds);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
       break;
     case PH_COMBINE:
-      for (int i = threadIdx.x; i < c.m_eff; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
+      for (int i = kp_tid(); i < c.m_eff; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
       __syncthreads();
       combine_pass<TB>(a, c.m_eff, coef, c.last != 0);
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        leader_combine(a);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
       break;
     case PH_FINISH:
       finish_pass(a, c.status == KP_STATUS_NONFINITE);
-      bar_arrive(a);
-      if (lead) {
-        bar_gather(a, k);
-        if (threadIdx.x == 0) cstore(&a.pub->phase, (int)PH_DONE);
-        bar_release(a, k);
-      } else {
-        bar_wait(a, k);
-      }
       break;
     default:
       break;
   }
+  bar_arrive(a);
+  if (!lead) {
+    bar_wait(a, k, &cur, &ok);
+    return;
+  }
+  // serial part (workgroup 0)
+  bar_gather(a, k, &ok);
+  if (!ok) return;
+  if (kp_tid() == 0) nxt = c;
+  switch (c.phase) {
+    case PH_STAGE:
+      leader_stage(a, red, nxt);
+      break;
+    case PH_STEP:
+      reduce_partials(a, 2 * c.j + 3, tv, grp);
+      scalar_step(a, c.j, tv, tabs, wk, nxt);
+      break;
+    case PH_CLOSE:
+      reduce_partials(a, 1, tv, grp);
+      leader_close(a, tv[0], nxt);
+      break;
+    case PH_EXPM:
+      expm_phase(a, lds, nxt);
+      break;
+    case PH_COMBINE:
+      leader_combine(a, nxt);
+      break;
+    case PH_FINISH:
+      if (kp_tid() == 0) nxt.phase = PH_DONE;
+      break;
+    default:
+      break;
+  }
+  bar_release(a, k, nxt, a.pub);
+  if (kp_tid() == 0) cur = nxt;
 }
 
 // The whole call (or, for the step-by-step entry, the steps up to stop_j).
@@ -170,20 +139,27 @@ template <typename TB>
 __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
   __shared__ double lds[kLdsDoubles];
   __shared__ double tabs[kTabDoubles];
-  __shared__ Ctrl c;
+  __shared__ Ctl cur, nxt;
+  __shared__ int ok;
   __shared__ unsigned s_k;
-  if (threadIdx.x == 0) s_k = cload(a.sync + 1);   // barriers released by earlier launches
+  if (kp_tid() == 0) {
+    // barriers released by earlier launches, and the control they announced
+    const unsigned long long w = cload(release_word(a));
+    s_k = (unsigned)(w >> 32);
+    cur = ctl_unpack((unsigned)w);
+    ok = aborted(a) ? 0 : 1;
+  }
   if (blockIdx.x == 0) load_tables(a, tabs);
   __syncthreads();
   unsigned k = s_k;
   for (;;) {
-    read_ctrl(a, &c);
-    if (c.phase == PH_DONE || c.abort_) break;
+    __syncthreads();
+    if (!ok || cur.phase == PH_DONE) break;
     if (arnoldi_only &&
-        (c.phase >= PH_EXPM || (c.phase == PH_STEP && c.j >= a.stop_j)))
+        (cur.phase >= PH_EXPM || (cur.phase == PH_STEP && cur.j >= a.stop_j)))
       break;
     ++k;
-    run_phase<TB>(a, lds, tabs, c, k);
+    run_phase<TB>(a, lds, tabs, cur, nxt, ok, k);
   }
 }
 
@@ -191,17 +167,15 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
 // so that entries outside their triangles read as zero.
 __global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
   State* st = a.st;
-  for (int i = threadIdx.x; i < kLdh * kMMax; i += blockDim.x) st->H[i] = 0.0;
-  for (int i = threadIdx.x; i < kLdt * kMMax; i += blockDim.x) {
+  for (int i = kp_tid(); i < kLdh * kMMax; i += blockDim.x) st->H[i] = 0.0;
+  for (int i = kp_tid(); i < kLdt * kMMax; i += blockDim.x) {
     st->Lm[i] = 0.0;
     st->Minv[i] = 0.0;
   }
-  for (int i = threadIdx.x; i < kMMax + 2; i += blockDim.x) a.pub->coef[i] = 0.0;
-  for (int i = threadIdx.x; i < a.nwg * kFlagStride; i += blockDim.x) a.flags[i] = 0u;
-  if (threadIdx.x != 0) return;
-  a.sync[0] = 0u;
-  a.sync[1] = 0u;
-  a.sync[2] = 0u;
+  for (int i = kp_tid(); i < kMMax + 2; i += blockDim.x) a.pub->coef[i] = 0.0;
+  for (int i = kp_tid(); i < a.nwg * kFlagStride; i += blockDim.x) a.flags[i] = 0u;
+  if (kp_tid() != 0) return;
+  for (int i = 0; i < 16; ++i) a.sync[i] = 0u;   // counters, release word (STAGE), abort
   Pub* pb = a.pub;
   pb->phase = PH_STAGE;
   pb->upd = 0;
@@ -505,10 +479,10 @@ int fill_info(kp_ctx* ctx, kp_info* info) {
   KP_HIP(ctx, hipMemcpy(&h, ctx->st, offsetof(State, sigma), hipMemcpyDeviceToHost));
   Pub pb;
   KP_HIP(ctx, hipMemcpy(&pb, ctx->pub, sizeof(Pub), hipMemcpyDeviceToHost));
-  unsigned flags[3] = {0, 0, 0};
+  unsigned flags[16] = {0};
   KP_HIP(ctx, hipMemcpy(flags, ctx->sync, sizeof(flags), hipMemcpyDeviceToHost));
   std::memset(info, 0, sizeof(*info));
-  info->status = flags[2] ? KP_STATUS_ABORTED : pb.status;
+  info->status = flags[kp::kSyncAbort] ? KP_STATUS_ABORTED : pb.status;
   info->substeps = h.substeps;
   info->rejected = h.rejected;
   info->arnoldi_steps = h.arnoldi_steps;
