@@ -24,7 +24,6 @@ Contents, each following the passage of arXiv:2410.14917 it implements:
   closed_form.py  closed forms that pin the above: DFT diagonalisation of
                   constant-coefficient periodic stencils and elementwise phi_k
                   for diagonal operators.
-  adjoint.py      gradients of a least-squares loss through the phi combination.
 
 Parity status of each function is stated in its docstring; every function here
 is pinned by a `-m "not gpu"` test against something other than itself.
