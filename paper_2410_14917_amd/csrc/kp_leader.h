@@ -86,25 +86,40 @@ __device__ __attribute__((always_inline)) inline void leader_stage(const Args& a
 }
 
 // ---- scalar step of Algorithm 4 --------------------------------------------
-// The leader keeps the correction matrices in LDS for the whole launch
-// (loaded once by load_tables, extended by one row per step, and mirrored in
-// the State for the host and for later launches).  Element (row r, column k)
-// of M^{-1} = (I + L)^{-1} / of L is at Mi[k * kTabLd + r] / Li[k * kTabLd + r];
-// sg[i] = sigma_i.
+// The leader keeps what its serial work reads in LDS for the whole launch
+// (loaded once by load_tables, updated as it changes, and mirrored in the
+// State for the host and for later launches): the correction matrices, with
+// element (row r, column k) of M^{-1} = (I + L)^{-1} / of L at
+// Mi[k * kTabLd + r] / Li[k * kTabLd + r], the unit scales sigma, the divisors
+// gamma, the squared norms ||A u_j||^2, and three controller flags.
 constexpr int kTabLd = kMMax + 1;
-constexpr int kTabDoubles = 2 * kMMax * kTabLd + kMMax + 8;
 
-__device__ inline void load_tables(const Args& a, double* tabs) {
+struct LeadLds {
+  double Mi[kMMax * kTabLd];
+  double Li[kMMax * kTabLd];
+  double sigma[kMMax + 8];
+  double gamma[kMMax + 8];
+  double wn2[kMMax + 8];
+  int fallback_cur, m_target, breakdown, pad_;
+};
+
+__device__ inline void load_tables(const Args& a, LeadLds& L) {
   const State* st = a.st;
-  double* Mi = tabs;
-  double* Li = tabs + kMMax * kTabLd;
-  double* sg = tabs + 2 * kMMax * kTabLd;
   for (int idx = kp_tid(); idx < kMMax * kMMax; idx += kThreads) {
     const int k = idx / kMMax, r = idx - k * kMMax;
-    Mi[k * kTabLd + r] = st->Minv[(int64_t)k * kLdt + r];
-    Li[k * kTabLd + r] = st->Lm[(int64_t)k * kLdt + r];
+    L.Mi[k * kTabLd + r] = st->Minv[(int64_t)k * kLdt + r];
+    L.Li[k * kTabLd + r] = st->Lm[(int64_t)k * kLdt + r];
   }
-  for (int i = kp_tid(); i < kMMax; i += kThreads) sg[i] = st->sigma[i];
+  for (int i = kp_tid(); i < kMMax + 2; i += kThreads) {
+    L.sigma[i] = st->sigma[i];
+    L.gamma[i] = st->gamma[i];
+    L.wn2[i] = st->wn2[i];
+  }
+  if (kp_tid() == 0) {
+    L.fallback_cur = st->fallback_cur;
+    L.m_target = st->m_target;
+    L.breakdown = st->breakdown;
+  }
   __syncthreads();
 }
 
@@ -143,13 +158,13 @@ __device__ inline double tri_mv(int jj, const double* tab, const double* v, doub
 // vector the matvec multiplied, so alpha = ||x_j|| is the lagged true norm and
 // H_{j,j-1} = gamma_{j-1} alpha (gamma = divisor applied to x_j when written).
 // Every thread of the workgroup calls this; wave 0 holds row i = lane.
-__device__ __attribute__((always_inline)) inline void scalar_step(const Args& a, int jj, const double* tv, double* tabs,
+__device__ __attribute__((always_inline)) inline void scalar_step(const Args& a, int jj, const double* tv, LeadLds& L,
                                    double* wk, Ctl& nx) {
   State* st = a.st;
   Pub* pb = a.pub;
-  double* Mi = tabs;
-  double* Li = tabs + kMMax * kTabLd;
-  double* sg = tabs + 2 * kMMax * kTabLd;
+  double* Mi = L.Mi;
+  double* Li = L.Li;
+  double* sg = L.sigma;
   double* sl = wk + kWkL;
   double* sb = wk + kWkB;
   double* sy = wk + kWkY;
@@ -167,6 +182,7 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
         nx.phase = (int)PH_FINISH;
       } else if (alpha == 0.0) {            // exact invariance already reached
         st->breakdown = 1;
+        L.breakdown = 1;
         nx.m_eff = jj;
         nx.upd = 0;
         st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
@@ -178,11 +194,12 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
     }
     return;
   }
-  if (jj > 0 && st->fallback_cur && alpha <= a.eps_bd * sqrt(st->wn2[jj - 1])) {
+  if (jj > 0 && L.fallback_cur && alpha <= a.eps_bd * sqrt(L.wn2[jj - 1])) {
     // the exact norm of the vector produced with the fallback is negligible:
     // lucky breakdown at the previous step (this step's products are unused)
     if (i == 0) {
       st->breakdown = 1;
+      L.breakdown = 1;
       st->H[(int64_t)(jj - 1) * kLdh + jj] = 0.0;
       nx.j = jj;
       nx.m_eff = jj;
@@ -260,9 +277,12 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
     st->sigma[jj] = sj;
     st->gamma[jj] = gam;
     st->wn2[jj] = wn2;
-    if (jj > 0) st->H[(int64_t)(jj - 1) * kLdh + jj] = st->gamma[jj - 1] * alpha;
+    L.gamma[jj] = gam;
+    L.wn2[jj] = wn2;
+    if (jj > 0) st->H[(int64_t)(jj - 1) * kLdh + jj] = L.gamma[jj - 1] * alpha;
     if (jj == 0) st->beta = alpha;
     st->fallback_cur = fallback;
+    L.fallback_cur = fallback;
     st->n_fallback += fallback;
     if (bad) {
       nx.status = (int)KP_STATUS_NONFINITE;
@@ -270,6 +290,7 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
     } else if (bd) {
       st->H[(int64_t)jj * kLdh + jj + 1] = 0.0;
       st->breakdown = 1;
+      L.breakdown = 1;
       st->arnoldi_steps += 1;
       nx.j = jj + 1;
       nx.m_eff = jj + 1;
@@ -281,7 +302,7 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
       nx.j = j;
       nx.m_eff = j;
       nx.upd = 1;
-      nx.phase = (int)((j >= st->m_target || j >= a.stop_j) ? PH_CLOSE : PH_STEP);
+      nx.phase = (int)((j >= L.m_target || j >= a.stop_j) ? PH_CLOSE : PH_STEP);
     }
   }
 }
@@ -290,12 +311,13 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
 // After the pending update produced x_j (j = completed steps), its exact norm
 // gives the last subdiagonal H_{j+1,j} = gamma_{j-1} ||x_j|| (the final
 // reduction of Algorithm 4).
-__device__ __attribute__((always_inline)) inline void leader_close(const Args& a, double nrm2, Ctl& nx) {
+__device__ __attribute__((always_inline)) inline void leader_close(const Args& a, double nrm2, LeadLds& L,
+                                                                  Ctl& nx) {
   if (kp_tid() != 0) return;
   State* st = a.st;
   const int j = nx.j;
   const double nrm = sqrt(nrm2);
-  st->H[(int64_t)(j - 1) * kLdh + j] = st->gamma[j - 1] * nrm;
+  st->H[(int64_t)(j - 1) * kLdh + j] = L.gamma[j - 1] * nrm;
   st->last_nrm2 = nrm2;
   nx.upd = 0;
   if (!isfinite(nrm2)) {
@@ -303,11 +325,12 @@ __device__ __attribute__((always_inline)) inline void leader_close(const Args& a
     nx.phase = (int)PH_FINISH;
     return;
   }
-  if (st->fallback_cur && nrm <= a.eps_bd * sqrt(st->wn2[j - 1])) {
+  if (L.fallback_cur && nrm <= a.eps_bd * sqrt(L.wn2[j - 1])) {
     st->H[(int64_t)(j - 1) * kLdh + j] = 0.0;
     st->breakdown = 1;
+    L.breakdown = 1;
   }
-  nx.phase = (int)((st->breakdown || j >= st->m_target) ? PH_EXPM : PH_STEP);
+  nx.phase = (int)((L.breakdown || j >= L.m_target) ? PH_EXPM : PH_STEP);
 }
 
 // ---- small exponential + substep controller (workgroup 0) -------------------
@@ -324,14 +347,15 @@ __device__ inline double tau_factor(double omega, int m) {
   return fmin(4.0, fmax(0.2, 0.9 * pow(omega, -1.0 / (double)(q + 1))));
 }
 
-__device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, double* lds, Ctl& nx) {
+__device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, double* lds, LeadLds& L,
+                                                                Ctl& nx) {
   __shared__ int s_dec;
   __shared__ double s_tau;
   State* st = a.st;
   Pub* pb = a.pub;
   const bool fixed = a.fixed_m > 0;
   const int m = nx.m_eff;
-  const bool happy = st->breakdown != 0;
+  const bool happy = L.breakdown != 0;
   const double t = st->t, beta = st->beta;
   double tau = st->tau;
   if (happy && !fixed) tau = a.h - t;
@@ -381,6 +405,7 @@ __device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, 
     if (kp_tid() == 0) {
       st->m_cur = min(2 * st->m_cur, a.m_max);
       st->m_target = st->m_cur;
+      L.m_target = st->m_cur;
       st->tau = tau;
       nx.upd = 0;
       nx.phase = (int)PH_STEP;
@@ -395,7 +420,7 @@ __device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, 
 }
 
 // ---- after the combine: advance time, next substep -------------------------
-__device__ __attribute__((always_inline)) inline void leader_combine(const Args& a, Ctl& nx) {
+__device__ __attribute__((always_inline)) inline void leader_combine(const Args& a, LeadLds& L, Ctl& nx) {
   if (kp_tid() != 0) return;
   State* st = a.st;
   const bool fixed = a.fixed_m > 0;
@@ -411,7 +436,7 @@ __device__ __attribute__((always_inline)) inline void leader_combine(const Args&
   st->m_last = m;
   const bool last = nx.last != 0;
   st->t = last ? a.h : st->t + tau;
-  if (st->breakdown) st->breakdowns += 1;
+  if (L.breakdown) st->breakdowns += 1;
   if (last) {
     nx.phase = (int)PH_DONE;
     return;
@@ -429,6 +454,8 @@ __device__ __attribute__((always_inline)) inline void leader_combine(const Args&
   st->tau = tn;
   st->breakdown = 0;
   st->m_target = fixed ? a.fixed_m : st->m_cur;
+  L.breakdown = 0;
+  L.m_target = st->m_target;
   nx.j = 0;
   nx.upd = 0;
   nx.phase = (int)PH_STEP;

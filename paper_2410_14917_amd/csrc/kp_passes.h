@@ -146,6 +146,8 @@ __device__ inline void tile_pairs(int64_t q0, int64_t pend, uint32_t* lo, bool* 
 
 // acc[r] += sum over the C columns i = i0, i0 + step, ... of coef[i] V_i(pair r).
 // All C * kR loads are issued before the first multiply-add.
+// The coefficients are read with coherent loads (they were published by the
+// leader), issued together with the column loads.
 template <typename TB, int C>
 __device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, int step,
                                  const double* coef, const uint32_t* lo, double2* acc) {
@@ -154,7 +156,7 @@ __device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, in
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const TB* vc = uniform_ptr(V + (int64_t)(i0 + c * step) * ld + t0);
-    ci[c] = coef[i0 + c * step];
+    ci[c] = cload(coef + i0 + c * step);
 #pragma unroll
     for (int r = 0; r < kR; ++r) v[c][r] = load_at(vc, lo[r] * (uint32_t)sizeof(TB));
   }
@@ -286,6 +288,22 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
   }
   const int64_t base = (int64_t)sg.plane * a.npt_pad;
   const int64_t xoff = (int64_t)sg.plane * a.npt;   // external plane offset
+  // B-hat x_tail / mu: the columns b_{p-c}, two at a time with all their
+  // loads issued before the first use (the first two go out with the
+  // stencil's loads)
+  double b0[2][kR][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c < a.p) {
+      const int64_t col = (int64_t)(a.p - c) * a.ldb + xoff - base;
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const int64_t e = t0 + lo[r];
+        b0[c][r][0] = a.B[col + e];
+        b0[c][r][1] = a.B[col + ((e + 1 < sg.end) ? e + 1 : e)];
+      }
+    }
+  }
 #pragma unroll
   for (int r = 0; r < kR; ++r) {
     const int64_t e = t0 + lo[r];
@@ -295,9 +313,19 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
     const double y = op_elem<TB, HL>(a, o, x, hl, sg.plane, v1 ? e + 1 : e, v1 ? q + 1 : q, v1);
     w[r].y = v1 ? y : 0.0;
   }
-  // B-hat x_tail / mu: the columns b_{p-c}, two at a time with all their
-  // loads issued before the first use
-  for (int c0 = 0; c0 < a.p; c0 += 2) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c < a.p) {
+      const double t = tc[c];
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const bool v1 = t0 + lo[r] + 1 < sg.end;
+        w[r].x += t * b0[c][r][0];
+        w[r].y += v1 ? t * b0[c][r][1] : 0.0;
+      }
+    }
+  }
+  for (int c0 = 2; c0 < a.p; c0 += 2) {
     double bv[2][kR][2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -484,6 +512,7 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
 }
 
 // ---- basis update (Algorithm 4: projection and normalisation) --------------
+// coef: the published coefficients (coherent global memory).
 // x_{j+1} = coef[jj+1] * w + sum_{i<=jj} coef[i] x_i, in place over column jj+1
 // (which holds w); the halo rows and the tail are published.  With want_norm,
 // partial slot 0 = ||x_{j+1}||^2 (the exact norm of the newest vector, needed
@@ -495,7 +524,7 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
-  const double cw = coef[jj + 1];
+  const double cw = cload(coef + jj + 1);
   const Rows o = own_rows(a);
   double ss = 0.0;
   const int ns = num_segs(a);
@@ -534,7 +563,8 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
 }
 
 // ---- combine: u = sum_{i<m} coef[i] x_i  (= beta V_m F, eq. kryexp) ----------
-// Also writes out = u_top when this is the last substep.
+// coef: the published coefficients (coherent global memory).  Also writes
+// out = u_top when this is the last substep.
 template <typename TB>
 __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a, int m, const double* coef, bool last) {
   const TB* V = reinterpret_cast<const TB*>(a.V);

@@ -44,18 +44,18 @@ constexpr int kLdsDoubles = (2 * kNmPad * kNmPad > kOffHl + kHaloCap) ? 2 * kNmP
 static_assert(kOffGrp + kRg * kKStride <= kOffCoef, "grp overlaps coef");
 static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
 static_assert(kOffTv + kKStride <= kOffHl, "tv overlaps the halo copy");
+static_assert(kLdsDoubles >= kNmPad * kGjLd, "the small exponential does not fit the phase buffer");
 
 // One phase of the call for this workgroup.  cur: control of the phase (LDS,
 // identical in every workgroup); nxt: the leader's control of the next phase;
 // ok: cleared when a bounded wait gives up (the launch is aborting).  On
 // return cur holds the control of the next phase.
 template <typename TB>
-__device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, double* tabs, Ctl& cur, Ctl& nxt, int& ok,
+__device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, LeadLds& L, Ctl& cur, Ctl& nxt, int& ok,
                           unsigned k) {
   double* sacc = lds + kOffSacc;
   double* grp = lds + kOffGrp;
   double* wk = lds + kOffWk;
-  double* coef = lds + kOffCoef;
   double* red = lds + kOffRed;
   double* tv = lds + kOffTv;
   double* hl = lds + kOffHl;
@@ -70,9 +70,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       // the update that produces x_j (coefficients of the previous scalar
       // step), then the matvec + grouped dots of step j: one grid-wide sync
       if (c.upd) {
-        for (int i = kp_tid(); i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
-        __syncthreads();
-        update_pass<TB>(a, c.j - 1, coef, red, false);
+        update_pass<TB>(a, c.j - 1, a.pub->coef, red, false);
         flag_publish(a, k);
         flag_wait_neighbours(a, k);
       }
@@ -82,14 +80,10 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
         matvec_dots_pass<TB, false>(a, c.j, sacc, hl);
       break;
     case PH_CLOSE:
-      for (int i = kp_tid(); i <= c.j; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
-      __syncthreads();
-      update_pass<TB>(a, c.j - 1, coef, red, true);
+      update_pass<TB>(a, c.j - 1, a.pub->coef, red, true);
       break;
     case PH_COMBINE:
-      for (int i = kp_tid(); i < c.m_eff; i += kThreads) coef[i] = cload(&a.pub->coef[i]);
-      __syncthreads();
-      combine_pass<TB>(a, c.m_eff, coef, c.last != 0);
+      combine_pass<TB>(a, c.m_eff, a.pub->coef, c.last != 0);
       break;
     case PH_FINISH:
       finish_pass(a, c.status == KP_STATUS_NONFINITE);
@@ -112,17 +106,17 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       break;
     case PH_STEP:
       reduce_partials(a, 2 * c.j + 3, tv, grp);
-      scalar_step(a, c.j, tv, tabs, wk, nxt);
+      scalar_step(a, c.j, tv, L, wk, nxt);
       break;
     case PH_CLOSE:
       reduce_partials(a, 1, tv, grp);
-      leader_close(a, tv[0], nxt);
+      leader_close(a, tv[0], L, nxt);
       break;
     case PH_EXPM:
-      expm_phase(a, lds, nxt);
+      expm_phase(a, lds, L, nxt);
       break;
     case PH_COMBINE:
-      leader_combine(a, nxt);
+      leader_combine(a, L, nxt);
       break;
     case PH_FINISH:
       if (kp_tid() == 0) nxt.phase = PH_DONE;
@@ -138,7 +132,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
 template <typename TB>
 __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
   __shared__ double lds[kLdsDoubles];
-  __shared__ double tabs[kTabDoubles];
+  __shared__ LeadLds lead;
   __shared__ Ctl cur, nxt;
   __shared__ int ok;
   __shared__ unsigned s_k;
@@ -149,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
     cur = ctl_unpack((unsigned)w);
     ok = aborted(a) ? 0 : 1;
   }
-  if (blockIdx.x == 0) load_tables(a, tabs);
+  if (blockIdx.x == 0) load_tables(a, lead);
   __syncthreads();
   unsigned k = s_k;
   for (;;) {
@@ -159,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
         (cur.phase >= PH_EXPM || (cur.phase == PH_STEP && cur.j >= a.stop_j)))
       break;
     ++k;
-    run_phase<TB>(a, lds, tabs, cur, nxt, ok, k);
+    run_phase<TB>(a, lds, lead, cur, nxt, ok, k);
   }
 }
 

@@ -299,6 +299,49 @@ def test_deterministic_and_exact_power_of_two_scaling():
     assert np.array_equal(y4, 4.0 * y1)
 
 
+# ---- FP32 basis (float32 storage and streams, float64 arithmetic) -----------
+
+FP32_TOL = 1e-5           # relative 2-norm bound of the FP32-basis results
+
+FP32_FIXED = [
+    (W.OP_BRUSSELATOR, 64, 48, 2, 32, 2),
+    (W.OP_ADR, 96, 80, 3, 40, 1),
+    (W.OP_ALLEN_CAHN, 80, 72, 2, 32, 2),
+]
+
+
+@pytest.mark.parametrize("case", FP32_FIXED)
+def test_fp32_basis_fixed_schedule(case):
+    kind, nx, ny, p, m, nsub = case
+    say(f"fp32 basis fixed kind={kind} {nx}x{ny} p={p} m={m} nsub={nsub}")
+    pr = W.random_problem(31, kind=kind, nx=nx, ny=ny, p=p, h=0.05, with_diag=True)
+    op, B = dev(pr)
+    with kp.Context(basis="f32", fixed_m=m, fixed_substeps=nsub) as ctx:
+        y32, info = ctx.phi_combo(op, B, pr.h, m_max=m, info=True)
+    with kp.Context(fixed_m=m, fixed_substeps=nsub) as ctx:
+        y64 = ctx.phi_combo(op, B, pr.h, m_max=m)
+    ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=m, fixed_substeps=nsub, m_max=m)
+    e_ref, e_64 = rel(y32.cpu().numpy(), ref), rel(y32.cpu().numpy(), y64.cpu().numpy())
+    say(f"  fp32 basis: rel err vs oracle {e_ref:.2e}, vs fp64 path {e_64:.2e}")
+    assert info["status"] == 0 and info["substeps"] == nsub
+    assert e_ref <= FP32_TOL and e_64 <= FP32_TOL
+
+
+def test_fp32_basis_adaptive_brusselator():
+    """Brusselator Jacobian (the FP32-basis workload's operator, small grid),
+    adaptive, tol 1e-6."""
+    pr = W.random_problem(32, kind=W.OP_BRUSSELATOR, nx=96, ny=80, p=2, h=0.01, nu=0.02)
+    op, B = dev(pr)
+    with kp.Context(basis="f32") as ctx:
+        y32, info = ctx.phi_combo(op, B, pr.h, tol=1e-6, m_max=64, info=True)
+    ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, 2, tol=1e-12, m_max=64)
+    e = rel(y32.cpu().numpy(), ref)
+    say(f"  fp32 basis adaptive: substeps {info['substeps']} rejected {info['rejected']} "
+        f"rel err vs oracle(tol 1e-12) {e:.2e}")
+    assert info["status"] == 0 and info["t_end"] == pr.h
+    assert e <= FP32_TOL
+
+
 def test_full_size_config2_fixed_substep():
     """Allen-Cahn 1024^2, one substep of exactly m = 64 (the microbenchmark's
     launch configuration), against the oracle element by element."""
