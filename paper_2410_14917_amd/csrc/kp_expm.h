@@ -67,20 +67,44 @@ __device__ inline void mm_tiles(int n, const double* A, const double* B, Tiles& 
   T.nt = (n + 15) >> 4;
   const int ntile = T.nt * T.nt;
   const int lr = lane & 15, lk = lane >> 4;
+  int arow[kTilesPerWave], bcol[kTilesPerWave];
+  bool act[kTilesPerWave];
 #pragma unroll
   for (int s = 0; s < kTilesPerWave; ++s) {
     T.c[s] = (kp_d4){0.0, 0.0, 0.0, 0.0};
     const int t = wv + kWaves * s;
-    if (t >= ntile) continue;
-    const int ti = t / T.nt, tj = t - ti * T.nt;
-    const int row = min(16 * ti + lr, kNmPad - 1);     // A operand: A[row][k]
-    const int col = min(16 * tj + lr, kNmPad - 1);     // B operand: B[k][col]
-    for (int k0 = 0; k0 < n; k0 += 4) {
-      const int k = k0 + lk;
-      const bool in = k < n;
-      const double av = in ? A[row * kNmPad + k] : 0.0;
-      const double bv = in ? B[k * kNmPad + col] : 0.0;
-      T.c[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, T.c[s], 0, 0, 0);
+    act[s] = t < ntile;                       // uniform over the wave
+    const int tt = act[s] ? t : 0;
+    const int ti = tt / T.nt, tj = tt - ti * T.nt;
+    arow[s] = min(16 * ti + lr, kNmPad - 1);    // A operand: A[row][k]
+    bcol[s] = min(16 * tj + lr, kNmPad - 1);    // B operand: B[k][col]
+  }
+  // the four accumulation chains are interleaved; the operands of step k0 + 4
+  // are loaded while step k0 multiplies
+  double av[kTilesPerWave], bv[kTilesPerWave];
+#pragma unroll
+  for (int s = 0; s < kTilesPerWave; ++s) {
+    const bool in = lk < n;
+    av[s] = in ? A[arow[s] * kNmPad + lk] : 0.0;
+    bv[s] = in ? B[lk * kNmPad + bcol[s]] : 0.0;
+  }
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    const int k = k0 + 4 + lk;
+    const bool in = k < n;
+    const int kc = in ? k : 0;
+    double an[kTilesPerWave], bn[kTilesPerWave];
+#pragma unroll
+    for (int s = 0; s < kTilesPerWave; ++s) {
+      an[s] = in ? A[arow[s] * kNmPad + kc] : 0.0;
+      bn[s] = in ? B[kc * kNmPad + bcol[s]] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < kTilesPerWave; ++s)
+      if (act[s]) T.c[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], T.c[s], 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < kTilesPerWave; ++s) {
+      av[s] = an[s];
+      bv[s] = bn[s];
     }
   }
 }
@@ -133,11 +157,10 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 // (ties and near-ties go to the smaller row index; every row still available
 // has a key >= 63, rows already used and rows past n have key 0).
 __device__ inline uint64_t pivot_key(double v, int n, int r, uint64_t used_lo, bool used64) {
-  if (r >= n) return 0;
-  const bool used = (r < 64) ? ((used_lo >> r) & 1u) : used64;
-  if (used) return 0;
+  const bool used = (r < 64) ? (((used_lo >> (r & 63)) & 1u) != 0) : used64;
   const uint64_t bits = (uint64_t)__double_as_longlong(fabs(v));
-  return (bits & ~(uint64_t)127) | (uint64_t)(127 - r);
+  const uint64_t key = (bits & ~(uint64_t)127) | (uint64_t)(127 - r);
+  return (r < n && !used) ? key : 0;
 }
 
 constexpr int kGjRows = (kNmPad + 3) / 4;   // rows of [q | p] per thread
@@ -173,16 +196,13 @@ __device__ inline void gauss_jordan(int n, const double* G, GjShared& sh, double
     const int par = k & 1;
     if (cA == k) {                                   // the owners of column k publish it
 #pragma unroll
-      for (int s = 0; s < kGjRows; ++s) {
-        const int r = rg + 4 * s;
-        if (r < n) sh.col[par][r] = gA[s];
-      }
+      for (int s = 0; s < kGjRows; ++s) sh.col[par][rg + 4 * s] = gA[s];
     }
     __syncthreads();
-    const uint64_t key =
-        umax64(pivot_key(sh.col[par][lane], n, lane, used_lo, used64),
-               pivot_key(lane + 64 < kNmPad ? sh.col[par][min(lane + 64, kNmPad - 1)] : 0.0, n,
-                         lane + 64, used_lo, used64));
+    const double c0 = sh.col[par][lane];
+    const double c1 = sh.col[par][min(lane + 64, kNmPad - 1)];
+    const uint64_t key = umax64(pivot_key(c0, n, lane, used_lo, used64),
+                                pivot_key(c1, n, lane + 64, used_lo, used64));
     const int P = 127 - (int)(wave_max_u64(key) & 127u);
     if (P < 64) used_lo |= (uint64_t)1 << P; else used64 = true;
     const double pval = sh.col[par][P];
@@ -206,14 +226,15 @@ __device__ inline void gauss_jordan(int n, const double* G, GjShared& sh, double
     const double inv = 1.0 / pval;
     const double pA = (hasA && cA > k) ? sh.row[par][cA] : 0.0;
     const double pB = hasB ? sh.row[par][cB] : 0.0;
+    double cv[kGjRows];
+#pragma unroll
+    for (int s = 0; s < kGjRows; ++s) cv[s] = sh.col[par][rg + 4 * s];   // all loads first
 #pragma unroll
     for (int s = 0; s < kGjRows; ++s) {
       const int r = rg + 4 * s;
-      if (r < n && r != P) {
-        const double f = sh.col[par][r] * inv;
-        gA[s] -= f * pA;
-        gB[s] -= f * pB;
-      }
+      const double f = (r < n && r != P) ? cv[s] * inv : 0.0;
+      gA[s] -= f * pA;
+      gB[s] -= f * pB;
     }
   }
   __syncthreads();

@@ -4,7 +4,10 @@
 //
 // Workgroup b owns grid rows [r0, r1) = [b*rows_per_wg, ...) of every species
 // plane, i.e. the internal elements [s*npt_pad + r0*nx, s*npt_pad + r1*nx) for
-// each plane s ("segments"); workgroup 0 also owns the augmented tail region.
+// each plane s ("segments").  Workgroup 0 also owns the p entries of the
+// augmented tail; they are handled column-parallel (one lane per basis column)
+// after its segments, so the tail costs one memory round trip rather than a
+// sweep over all columns.
 // Elements are processed in pairs (16-byte accesses); segment starts are even
 // by construction, and an odd segment end leaves one padding element (kept
 // zero) in the last pair.
@@ -105,26 +108,17 @@ __device__ inline Rows own_rows(const Args& a) {
   return o;
 }
 
-// One owned segment: elements [beg, end) of plane `plane`, or the tail.
+// One owned segment: elements [beg, end) of plane `plane`.
 struct Seg {
   int64_t beg, end;
   int plane;
-  bool tail;
 };
 
-__device__ inline int num_segs(const Args& a) { return a.nplanes + (blockIdx.x == 0 ? 1 : 0); }
+__device__ inline int num_segs(const Args& a) { return a.nplanes; }
 
 __device__ inline Seg seg_at(const Args& a, const Rows& o, int si) {
-  if (si < a.nplanes) {
-    const int64_t base = (int64_t)si * a.npt_pad;
-    return Seg{base + (int64_t)o.r0 * a.nx, base + (int64_t)o.r1 * a.nx, si, false};
-  }
-  return Seg{a.tail_off, a.tail_off + kTailPad, 0, true};
-}
-
-// Index of the halo slot of (workgroup w, plane s, side: 0 first row, 1 last row).
-__device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix) {
-  return ((int64_t)(w * a.nplanes + s) * 2 + side) * a.nx + ix;
+  const int64_t base = (int64_t)si * a.npt_pad;
+  return Seg{base + (int64_t)o.r0 * a.nx, base + (int64_t)o.r1 * a.nx, si};
 }
 
 constexpr int kR = 4;    // element pairs per thread per sub-tile
@@ -169,17 +163,19 @@ __device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, in
     }
 }
 
+// Index of the halo slot of (workgroup w, plane s, side: 0 first row, 1 last row).
+__device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix) {
+  return ((int64_t)(w * a.nplanes + s) * 2 + side) * a.nx + ix;
+}
+
 // A producer of a vector that the next matvec multiplies publishes, with
 // coherent stores, the elements of the first and last row of each owned plane
-// segment (the stencil halo of the neighbouring workgroups) and the tail
-// (workgroup 0).  Called for the element pair (e, e+1) of segment sg with the
-// values as stored; lanes outside the boundary rows store nothing.
+// segment (the stencil halo of the neighbouring workgroups).  Called for the
+// element pair (e, e+1) of segment sg with the values as stored; lanes outside
+// the boundary rows store nothing.  (The tail is published by tail_update /
+// tail_combine.)
 __device__ inline void publish_elem(const Args& a, const Seg& sg, int64_t e, double v) {
   if (e >= sg.end) return;
-  if (sg.tail) {
-    cstore(a.tx + (e - a.tail_off), v);
-    return;
-  }
   const int64_t off = e - sg.beg, last0 = sg.end - sg.beg - a.nx;
   if (off < a.nx) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 0, (int)off), v);
   if (off >= last0) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 1, (int)(off - last0)), v);
@@ -187,7 +183,7 @@ __device__ inline void publish_elem(const Args& a, const Seg& sg, int64_t e, dou
 
 __device__ inline void publish_pair(const Args& a, const Seg& sg, int64_t e, double v0,
                                     double v1) {
-  if (sg.tail || e - sg.beg < a.nx || e + 1 >= sg.end - a.nx) {
+  if (e - sg.beg < a.nx || e + 1 >= sg.end - a.nx) {
     publish_elem(a, sg, e, v0);
     publish_elem(a, sg, e + 1, v1);
   }
@@ -267,25 +263,13 @@ __device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x,
   return s ? lap + a12 * xo + a22 * c : lap + a11 * c + a21 * xo;
 }
 
-// (Atilde x) on the kR pairs of a sub-tile of segment sg.  Grid part:
-// A x_top + sum_c tc[c] b_{p-c}; tail part: K x_tail (upward shift); zero in
-// the padding.
+// (Atilde x) on the kR pairs of a sub-tile of plane segment sg:
+// A x_top + sum_c tc[c] b_{p-c} (the tail rows, K x_tail, are done by
+// tail_matvec_dots); zero in the padding.
 template <typename TB, bool HL>
 __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, const Src<TB>& x,
                                 const double* hl, int64_t t0, const uint32_t* lo,
                                 const double* tc, double2* w) {
-  if (sg.tail) {
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      const int64_t e = t0 + lo[r];
-      const int64_t k = e - a.tail_off;
-      const double2 nx2 = x.pair(e + 2 < sg.end ? e + 2 : e);
-      const double v1 = x(e + 1);
-      w[r].x = (k + 1 < a.p) ? v1 : 0.0;
-      w[r].y = (k + 2 < a.p) ? nx2.x : 0.0;
-    }
-    return;
-  }
   const int64_t base = (int64_t)sg.plane * a.npt_pad;
   const int64_t xoff = (int64_t)sg.plane * a.npt;   // external plane offset
   // B-hat x_tail / mu: the columns b_{p-c}, two at a time with all their
@@ -354,6 +338,100 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
   }
 }
 
+// ---- the augmented tail (workgroup 0) -----------------------------------------
+// The p tail entries of every vector are handled column-parallel: lane i of
+// wave 0 takes basis column i (and i + 64), so the work is one memory round
+// trip and at most kPMax wave reductions.
+
+// Tail rows of the matvec of step jj (w_tail = K x_tail, the upward shift;
+// x_tail is also stored at the first step) and their share of the inner
+// products: x_i . x and x_i . w (slots 2i, 2i+1 of wave 0's row of sacc) and
+// x . x, x . w, w . w (slots 2jj .. 2jj+2).
+template <typename TB>
+__device__ inline void tail_matvec_dots(const Args& a, int jj, const Src<TB>& x, TB* V,
+                                        double* sacc) {
+  const int t = kp_tid();
+  if (t >= 64) return;
+  const int64_t T0 = a.tail_off, ld = a.ld;
+  const int p = a.p;
+  TB* xcol = V + (int64_t)jj * ld;
+  TB* wcol = V + (int64_t)(jj + 1) * ld;
+  double xt[kPMax], wt[kPMax];
+#pragma unroll
+  for (int k = 0; k < kPMax; ++k) xt[k] = (k < p) ? x(T0 + k) : 0.0;
+#pragma unroll
+  for (int k = 0; k < kPMax; ++k) wt[k] = (k + 1 < kPMax && k + 1 < p) ? xt[k + 1] : 0.0;
+  if (t < p) {
+    wcol[T0 + t] = (TB)((t + 1 < p) ? x(T0 + t + 1) : 0.0);
+    if (jj == 0) xcol[T0 + t] = (TB)x(T0 + t);
+  }
+  if (t < jj) {
+    const TB* vc = V + (int64_t)t * ld + T0;
+    double sx = 0.0, sw = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPMax; ++k) {
+      if (k < p) {
+        const double v = (double)vc[k];
+        sx += v * xt[k];
+        sw += v * wt[k];
+      }
+    }
+    sacc[2 * t] += sx;
+    sacc[2 * t + 1] += sw;
+  }
+  if (t == 0) {
+    double xx = 0.0, xw = 0.0, ww = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPMax; ++k) {
+      xx += xt[k] * xt[k];
+      xw += xt[k] * wt[k];
+      ww += wt[k] * wt[k];
+    }
+    sacc[2 * jj] += xx;
+    sacc[2 * jj + 1] += xw;
+    sacc[2 * jj + 2] += ww;
+  }
+}
+
+// Tail of u = sum_{i < nc} c_i V_i, where c_i = coef[i] (coherent loads) and,
+// when extra_col >= 0, column extra_col enters with weight cextra.  Result in
+// place of out_col's tail (or of a.u when out_col is null), published to the
+// tail copy when publish.  Returns sum y_k^2 in lane 0 of wave 0.
+template <typename TB, typename TO>
+__device__ inline double tail_combine_cols(const Args& a, const TB* V, int nc, const double* coef,
+                                           int extra_col, double cextra, TO* out, bool publish) {
+  const int t = kp_tid();
+  if (t >= 64) return 0.0;
+  const int64_t T0 = a.tail_off, ld = a.ld;
+  const int p = a.p;
+  double part[kPMax];
+#pragma unroll
+  for (int k = 0; k < kPMax; ++k) part[k] = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = t + 64 * h;
+    const bool on = i < nc || i == extra_col;
+    const double ci = on ? ((i == extra_col) ? cextra : cload(coef + i)) : 0.0;
+    const TB* vc = V + (int64_t)(on ? i : 0) * ld + T0;
+#pragma unroll
+    for (int k = 0; k < kPMax; ++k)
+      if (k < p && on) part[k] += ci * (double)vc[k];
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPMax; ++k) {
+    if (k < p) {
+      const double y = rnd<TO>(wave_sum(part[k]));
+      if (t == 0) {
+        out[T0 + k] = (TO)y;
+        if (publish) cstore(a.tx + k, y);
+        ss += y * y;
+      }
+    }
+  }
+  return ss;
+}
+
 // ---- stage: u = [b_0; 0] (the leader adds mu e_p), max |b_k| for k >= 1 -----
 // Partial slots: [0] = max |b_k|, [1] = 1 if a non-finite entry was seen.
 __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, double* red) {
@@ -364,7 +442,7 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
     const Seg sg = seg_at(a, o, si);
     for (int64_t e = sg.beg + kp_tid(); e < ((sg.end + 1) & ~(int64_t)1); e += kThreads) {
       double v = 0.0;
-      if (!sg.tail && e < sg.end) {
+      if (e < sg.end) {
         const int64_t eext = e - (int64_t)sg.plane * a.npt_pad + (int64_t)sg.plane * a.npt;
         v = a.B[eext];
         if (!isfinite(v)) bad = 1.0;
@@ -375,7 +453,7 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
         }
       }
       a.u[e] = v;
-      if (!sg.tail) publish_elem(a, sg, e, v);   // the tail is completed by the leader
+      publish_elem(a, sg, e, v);   // the tail is staged by the leader
     }
   }
   mx = block_max(mx, red);
@@ -502,6 +580,7 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
     sacc[wv * kKStride + 2 * jj + 1] += sxw;
     sacc[wv * kKStride + 2 * jj + 2] += sww;
   }
+  if (blockIdx.x == 0) tail_matvec_dots<TB>(a, jj, x, V, sacc);
   __syncthreads();
   const int nslot = 2 * jj + 3;
   for (int k = kp_tid(); k < nslot; k += kThreads) {
@@ -556,6 +635,8 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
       }
     }
   }
+  if (blockIdx.x == 0)
+    ss += tail_combine_cols<TB, TB>(a, V, jj + 1, coef, jj + 1, cw, wcol, true);
   if (want_norm) {
     ss = block_sum(ss, red);
     if (kp_tid() == 0) cstore(a.part + (int64_t)blockIdx.x * kKStride, ss);
@@ -592,7 +673,7 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
           const int64_t e = t0 + lo[r];
           *reinterpret_cast<double2*>(a.u + e) = acc[r];
           if (!last) publish_pair(a, sg, e, acc[r].x, acc[r].y);
-          if (last && !sg.tail) {
+          if (last) {
             if (e < sg.end) a.out[e + shift] = acc[r].x;
             if (e + 1 < sg.end) a.out[e + 1 + shift] = acc[r].y;
           }
@@ -600,6 +681,7 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
       }
     }
   }
+  if (blockIdx.x == 0) tail_combine_cols<TB, double>(a, V, m, coef, -1, 0.0, a.u, !last);
 }
 
 // ---- finish: out = u_top (or NaN when the input was not finite) -------------
