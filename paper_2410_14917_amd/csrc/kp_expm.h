@@ -68,43 +68,41 @@ __device__ inline void mm_tiles(int n, const double* A, const double* B, Tiles& 
   const int ntile = T.nt * T.nt;
   const int lr = lane & 15, lk = lane >> 4;
   int arow[kTilesPerWave], bcol[kTilesPerWave];
-  bool act[kTilesPerWave];
 #pragma unroll
   for (int s = 0; s < kTilesPerWave; ++s) {
     T.c[s] = (kp_d4){0.0, 0.0, 0.0, 0.0};
-    const int t = wv + kWaves * s;
-    act[s] = t < ntile;                       // uniform over the wave
-    const int tt = act[s] ? t : 0;
-    const int ti = tt / T.nt, tj = tt - ti * T.nt;
+    // tiles past the last one compute on a valid clamped tile and are never
+    // written (tiles_for_each skips them), so the four chains run unbranched
+    const int t = min(wv + kWaves * s, ntile - 1);
+    const int ti = t / T.nt, tj = t - ti * T.nt;
     arow[s] = min(16 * ti + lr, kNmPad - 1);    // A operand: A[row][k]
     bcol[s] = min(16 * tj + lr, kNmPad - 1);    // B operand: B[k][col]
   }
   // the four accumulation chains are interleaved; the operands of step k0 + 4
-  // are loaded while step k0 multiplies
+  // are loaded while step k0 multiplies; entries past n enter as zeros
   double av[kTilesPerWave], bv[kTilesPerWave];
 #pragma unroll
   for (int s = 0; s < kTilesPerWave; ++s) {
-    const bool in = lk < n;
-    av[s] = in ? A[arow[s] * kNmPad + lk] : 0.0;
-    bv[s] = in ? B[lk * kNmPad + bcol[s]] : 0.0;
+    const double ta = A[arow[s] * kNmPad + lk], tb = B[lk * kNmPad + bcol[s]];
+    av[s] = (lk < n) ? ta : 0.0;
+    bv[s] = (lk < n) ? tb : 0.0;
   }
   for (int k0 = 0; k0 < n; k0 += 4) {
     const int k = k0 + 4 + lk;
-    const bool in = k < n;
-    const int kc = in ? k : 0;
+    const int kc = min(k, kNmPad - 1);
     double an[kTilesPerWave], bn[kTilesPerWave];
 #pragma unroll
     for (int s = 0; s < kTilesPerWave; ++s) {
-      an[s] = in ? A[arow[s] * kNmPad + kc] : 0.0;
-      bn[s] = in ? B[kc * kNmPad + bcol[s]] : 0.0;
+      an[s] = A[arow[s] * kNmPad + kc];
+      bn[s] = B[kc * kNmPad + bcol[s]];
     }
 #pragma unroll
     for (int s = 0; s < kTilesPerWave; ++s)
-      if (act[s]) T.c[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], T.c[s], 0, 0, 0);
+      T.c[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], T.c[s], 0, 0, 0);
 #pragma unroll
     for (int s = 0; s < kTilesPerWave; ++s) {
-      av[s] = an[s];
-      bv[s] = bn[s];
+      av[s] = (k < n) ? an[s] : 0.0;
+      bv[s] = (k < n) ? bn[s] : 0.0;
     }
   }
 }

@@ -264,6 +264,7 @@ __device__ inline bool spin_until(const Args& a, const unsigned* ctr, unsigned t
   if (cload(ctr) >= target) return true;
   const int64_t t0 = wall_clock64();
   for (unsigned it = 1;; ++it) {
+    __builtin_amdgcn_s_sleep(1);          // back off: fewer polls of the shared line
     if (cload(ctr) >= target) return true;
     if ((it & 31u) == 0u && (aborted(a) || wait_expired(a, t0))) return false;
   }
@@ -310,6 +311,7 @@ __device__ inline void bar_wait(const Args& a, unsigned k, Ctl* cur, int* ok) {
     if ((unsigned)(w >> 32) < k) {
       const int64_t t0 = wall_clock64();
       for (unsigned it = 1;; ++it) {
+        __builtin_amdgcn_s_sleep(1);
         w = cload(rw);
         if ((unsigned)(w >> 32) >= k) break;
         if ((it & 31u) == 0u && (aborted(a) || wait_expired(a, t0))) {
@@ -342,6 +344,7 @@ __device__ inline void flag_wait_neighbours(const Args& a, unsigned k) {
     const unsigned* f0 = a.flags;
     int64_t t0 = 0;
     for (unsigned it = 0;; ++it) {
+      if (it) __builtin_amdgcn_s_sleep(1);
       const unsigned vp = cload(fp), vn = cload(fn), v0 = cload(f0);
       if (vp >= k && vn >= k && v0 >= k) break;
       if (it == 0) t0 = wall_clock64();
