@@ -61,6 +61,19 @@ def measured_traffic():
         return None
 
 
+def basis_bytes_per_call(schedule, p, c, n, s):
+    """Algorithmic HBM bytes of one call with basis elements of s bytes (the
+    state vector, B, the fields and out stay float64): per Arnoldi step jj the
+    matvec reads x_j (s), p columns of B and c fields (8 each) and jj basis
+    columns (s), writes w (s); the update reads w and jj+1 columns (s) and
+    writes x_{j+1} (s); combine reads m columns (s) and writes u (8); stage
+    reads p+1 columns and writes u (8); the last combine writes out (8)."""
+    total = 8 * ((p + 1) + 1)
+    for _, m in schedule:
+        total += sum(s * (2 * jj + 4) + 8 * (p + c) for jj in range(m)) + s + s * m + 8
+    return (total + 8) * n
+
+
 def vectors_per_call(schedule, p, c):
     """Algorithmic vector passes (each N float64) of one phi_combo call.
 
@@ -85,6 +98,8 @@ def main():
     ap.add_argument("--basis", default="f64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-m microbenchmark")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32-basis leg (2 x 2048^2 Brusselator)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -203,6 +218,47 @@ def main():
         }
         fctx.close()
     ctx.close()
+
+    # ---- FP32 basis against the FP64 path (2 x 2048^2 Brusselator) ----------
+    if not args.no_fp32:
+        del B, out
+        torch.cuda.empty_cache()
+        p3 = W.config3()
+        op3 = kp.Operator.from_host(p3.op, device=dev)
+        B3 = torch.as_tensor(np.ascontiguousarray(p3.B.T), device=dev)
+        o3 = torch.empty(p3.op.n, dtype=torch.float64, device=dev)
+        leg = {"workload": f"Brusselator Jacobian (A=1, B=3, D=0.02/0.01), 2x2048^2, "
+                           f"N={p3.op.n}, p={p3.p}, h={p3.h}, tol={p3.tol}, m<=64 adaptive"}
+        ys = {}
+        for basis, sz in (("f64", 8), ("f32", 4)):
+            c3 = kp.Context(orth=args.orth, basis=basis, stream=stream)
+            _, inf3 = c3.phi_combo(op3, B3, p3.h, tol=p3.tol, m_max=p3.m_max, out=o3, info=True)
+            sch3 = c3.schedule()
+            nrep = 3
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+            torch.cuda.synchronize()
+            for k in range(nrep):
+                e0[k].record(stream)
+                c3.phi_combo(op3, B3, p3.h, tol=p3.tol, m_max=p3.m_max, out=o3)
+                e1[k].record(stream)
+            torch.cuda.synchronize()
+            ms3 = float(np.mean([a.elapsed_time(b) for a, b in zip(e0, e1)]))
+            ys[basis] = o3.double().cpu().numpy().copy()
+            byts = basis_bytes_per_call(sch3, p3.p, 2, p3.op.n, sz)
+            leg[basis] = {"ms_per_call": round(ms3, 3), "arnoldi_steps": inf3["arnoldi_steps"],
+                          "substeps": inf3["substeps"], "rejected": inf3["rejected"],
+                          "arnoldi_steps_per_s": round(inf3["arnoldi_steps"] / (ms3 * 1e-3), 1),
+                          "modelled_GBps": round(byts / (ms3 * 1e-3) / 1e9, 1),
+                          "frac": round(byts / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "status": inf3["status"]}
+            c3.close()
+            print(f"[bench] fp32 leg {basis}: {leg[basis]}", file=sys.stderr, flush=True)
+        leg["rel_err_f32_vs_f64"] = float(np.linalg.norm(ys["f32"] - ys["f64"]) /
+                                          np.linalg.norm(ys["f64"]))
+        leg["speedup_f32_over_f64"] = round(leg["f64"]["ms_per_call"] / leg["f32"]["ms_per_call"], 3)
+        result["fp32_basis"] = leg
+        del B3, o3
 
     # ---- CPU oracle baseline (bounded sample) --------------------------------
     if not args.no_cpu:
