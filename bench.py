@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-m microbenchmark")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the FP32-basis leg (2 x 2048^2 Brusselator)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint leg (advection-diffusion 1024^2, least-squares loss)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -259,6 +261,74 @@ def main():
         leg["speedup_f32_over_f64"] = round(leg["f64"]["ms_per_call"] / leg["f32"]["ms_per_call"], 3)
         result["fp32_basis"] = leg
         del B3, o3
+
+    # ---- adjoint: loss ||phi_combo - y||^2, gradients in B and nu ------------
+    if not args.no_adjoint:
+        from paper_2410_14917_amd import autograd as kpa
+        torch.cuda.empty_cache()
+        p5 = W.config5()
+        op5 = kp.Operator.from_host(p5.op, device=dev)
+        B5 = torch.as_tensor(np.ascontiguousarray(p5.B.T), device=dev).requires_grad_(True)
+        nu5 = torch.tensor(p5.op.nu, dtype=torch.float64, device=dev, requires_grad=True)
+        y5 = torch.as_tensor(p5.y, device=dev)
+
+        def loss5():
+            return ((kpa.phi_combo(B5, nu5, op5, p5.h, tol=p5.tol, m_max=p5.m_max,
+                                   orth=args.orth) - y5) ** 2).sum()
+
+        def timed(fn, nrep=3):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(nrep):
+                fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t) / nrep
+
+        def fwd():
+            with torch.no_grad():
+                loss5()
+
+        def fwd_bwd():
+            B5.grad = nu5.grad = None
+            loss5().backward()
+
+        ms_f, ms_fb = timed(fwd), timed(fwd_bwd)
+        # the solves one by one (forward, the p+1 transposed solves, the tangent)
+        c5 = kp.Context(orth=args.orth, stream=stream)
+        opt5 = kp.Operator(op5.kind, op5.nx, op5.ny, nu=op5.nu, ax=op5.ax, ay=op5.ay,
+                           react=op5.react, transpose=True, dx=op5.dx, dy=op5.dy)
+        dop5 = kp.Operator(op5.kind, op5.nx, op5.ny, nu=1.0, dx=op5.dx, dy=op5.dy)
+        Bd = B5.detach()
+        g5 = torch.randn(p5.op.n, dtype=torch.float64, device=dev)
+        solves = {}
+        _, inf = c5.phi_combo(op5, Bd, p5.h, tol=p5.tol, m_max=p5.m_max, info=True)
+        solves["forward"] = (timed(lambda: c5.phi_combo(op5, Bd, p5.h, tol=p5.tol,
+                                                        m_max=p5.m_max)), inf)
+        for k in range(p5.p + 1):
+            Bk = torch.zeros((k + 1, p5.op.n), dtype=torch.float64, device=dev)
+            Bk[k] = g5
+            _, inf = c5.phi_combo(opt5, Bk, p5.h, tol=p5.tol, m_max=p5.m_max, info=True)
+            solves[f"transposed_k{k}"] = (timed(lambda: c5.phi_combo(
+                opt5, Bk, p5.h, tol=p5.tol, m_max=p5.m_max)), inf)
+        _, _, inf = c5.phi_combo_tangent(op5, dop5, Bd, p5.h, tol=p5.tol, m_max=p5.m_max,
+                                         info=True)
+        solves["tangent"] = (timed(lambda: c5.phi_combo_tangent(
+            op5, dop5, Bd, p5.h, tol=p5.tol, m_max=p5.m_max)), inf)
+        c5.close()
+        kpa.release_contexts()
+        result["adjoint"] = {
+            "workload": f"advection-diffusion nu={p5.op.nu}, a=({p5.op.ax},{p5.op.ay}), "
+                        f"{p5.op.nx}x{p5.op.ny}, p={p5.p}, h={p5.h}, tol={p5.tol}, "
+                        f"loss ||phi_combo - y||^2, gradients in b_0..b_{p5.p} and nu",
+            "forward_ms": round(ms_f, 3), "forward_backward_ms": round(ms_fb, 3),
+            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3),
+            "solves": {k: {"ms": round(v[0], 3), "arnoldi_steps": v[1]["arnoldi_steps"],
+                           "substeps": v[1]["substeps"], "status": v[1]["status"]}
+                       for k, v in solves.items()},
+        }
+        print(f"[bench] adjoint leg: {result['adjoint']}", file=sys.stderr, flush=True)
+        del B5, y5
 
     # ---- CPU oracle baseline (bounded sample) --------------------------------
     if not args.no_cpu:

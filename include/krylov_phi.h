@@ -159,6 +159,30 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
                  int64_t ldb, double h, double tol, int32_t m_max,
                  double* out, kp_info* info);
 
+/*
+ * Directional derivative of the phi combination with respect to the operator
+ * (tangent mode, for gradients with respect to operator coefficients):
+ *     out  = sum_{k=0}^{p} h^k phi_k(h A) b_k                (as kp_phi_combo)
+ *     dout = d/de sum_{k=0}^{p} h^k phi_k(h (A + e dA)) b_k   at e = 0.
+ * With Atilde the augmented matrix of Section 2.1 and Etilde = [[dA, 0], [0, 0]],
+ * out and dout are the top blocks of the two halves of exp(h M) [0; z] for the
+ * block matrix M = [[Atilde, Etilde], [0, Atilde]] (the block-triangular
+ * exponential whose upper-right block is the Frechet derivative of exp, Van
+ * Loan, IEEE Trans. Automat. Control 23 (1978)); one Krylov solve of Section 3
+ * on vectors of length 2(N + p), substepped and controlled as kp_phi_combo.
+ *   A  : KP_OP_ADR or KP_OP_ALLEN_CAHN (one species plane).
+ *   dA : same kind, grid and transpose flag as A; its nu, ax, ay, react give
+ *        the direction (dA = nu Lap - ax Dx - ay Dy + react I; transposed with
+ *        A); field0/field1 must be NULL.
+ *   p  : 0 <= 2p <= KP_PMAX.
+ *   out, dout: device, N doubles each, disjoint from B, the fields and each other.
+ * Errors: KP_EINVAL, KP_EUNSUPPORTED (other kinds, fields in dA, p too large),
+ * KP_ENOMEM, KP_EHIP.
+ */
+int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const double* B,
+                         int32_t p, int64_t ldb, double h, double tol, int32_t m_max,
+                         double* out, double* dout, kp_info* info);
+
 /* Copy the (tau_i, m_i) of the accepted substeps of the last call into host
  * arrays of capacity cap; returns the number copied (>= 0) or a KP_E code. */
 int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap);

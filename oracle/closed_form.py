@@ -8,6 +8,11 @@
   (the transpose flips the sign of the advection term).  Hence
       sum_k h^k phi_k(hA) b_k = sum_k h^k IDFT(phi_k(h lambda) DFT(b_k)).
 * Diagonal A: phi_k acts elementwise (oracle.phi.phi_combo_diag).
+* Derivative in the diffusion coefficient: d lambda / d nu is the Laplacian's
+  eigenvalue, and d/dz phi_k(z) = phi_k(z) - k phi_{k+1}(z) (differentiate
+  the integral definition: the factor (1 - s) splits into phi_k and
+  k phi_{k+1}), so d/dnu h^k phi_k(h lambda) = h^{k+1} (phi_k - k phi_{k+1})
+  (h lambda) dlambda/dnu.
 """
 from __future__ import annotations
 
@@ -45,3 +50,23 @@ def adr_apply_spectral(op, x: np.ndarray) -> np.ndarray:
     lam = adr_eigenvalues(op)
     X = np.fft.fft2(x.reshape(op.ny, op.nx))
     return np.real(np.fft.ifft2(lam * X)).reshape(-1)
+
+
+def adr_laplacian_eigenvalues(op) -> np.ndarray:
+    """Eigenvalues of the 5-point Laplacian on the (ny, nx) DFT grid."""
+    tx = 2.0 * np.pi * np.fft.fftfreq(op.nx)
+    ty = 2.0 * np.pi * np.fft.fftfreq(op.ny)
+    TX, TY = np.meshgrid(tx, ty)
+    return (2.0 * np.cos(TX) - 2.0) / op.dx**2 + (2.0 * np.cos(TY) - 2.0) / op.dy**2
+
+
+def adr_phi_combo_dnu(op, B: np.ndarray, h: float, p: int) -> np.ndarray:
+    """d/dnu of sum_k h^k phi_k(h A(nu)) b_k for the constant-coefficient ADR."""
+    lam = adr_eigenvalues(op)
+    dlam = adr_laplacian_eigenvalues(op)
+    acc = np.zeros((op.ny, op.nx), dtype=complex)
+    for k in range(p + 1):
+        bk = B[:, k].reshape(op.ny, op.nx)
+        dphi = phi_scalar(k, h * lam) - k * phi_scalar(k + 1, h * lam)
+        acc += (h ** (k + 1)) * dphi * dlam * np.fft.fft2(bk)
+    return np.real(np.fft.ifft2(acc)).reshape(-1)

@@ -115,27 +115,14 @@ def _basis(arn, m):
     return arn.basis()[:, :m]
 
 
-def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
-              m_max: int = 64, fixed_m: int = 0, fixed_substeps: int = 0,
-              orth: str = "mgs", tform: str = "gsmgs", max_substeps: int = 2000,
-              delta: float = 1e-10, eps_bd: float = 1e-12, want_orth_loss=False,
-              mu: float = None):
-    """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4)."""
-    n = op.n
+def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
+          fixed_m: int = 0, fixed_substeps: int = 0, orth: str = "mgs",
+          tform: str = "gsmgs", max_substeps: int = 2000, delta: float = 1e-10,
+          eps_bd: float = 1e-12, want_orth_loss=False):
+    """exp(h M) w for the operator M given by apply(x) = M x, by substepped
+    Krylov projections with the schedules above.  Returns (vector, Info)."""
+    n = len(w)
     info = Info()
-    B = np.asarray(B, dtype=np.float64)
-    if not np.all(np.isfinite(B[:, :p + 1])):
-        info.status = STATUS_NONFINITE
-        return np.full(n, np.nan), info
-    if mu is None:
-        mu = balance_scale(B, p)
-    w = start_vector(B, p, mu)
-    if h == 0.0:
-        return B[:, 0].copy(), info
-
-    def apply(x):
-        return aug_apply(op, B, p, mu, x)
-
     fixed = fixed_m > 0
     if fixed:
         nsub = max(1, fixed_substeps)
@@ -197,7 +184,7 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
             tau = tau * min(F_MAX, max(F_MIN, F_SAFE * omega ** (-1.0 / (q + 1))))
             if tau <= 1e-14 * h:
                 info.status = STATUS_NOT_CONVERGED
-                return w[:n].copy(), info
+                return w.copy(), info
         if want_orth_loss:
             Vb = _basis(arn, mb)
             info.orth_loss = max(info.orth_loss,
@@ -218,4 +205,32 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
             fac = F_MAX if omega == 0.0 else min(
                 F_MAX, max(F_MIN, F_SAFE * omega ** (-1.0 / (q + 1))))
             tau = tau * fac
-    return w[:n].copy(), info
+    return w.copy(), info
+
+
+def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
+              m_max: int = 64, fixed_m: int = 0, fixed_substeps: int = 0,
+              orth: str = "mgs", tform: str = "gsmgs", max_substeps: int = 2000,
+              delta: float = 1e-10, eps_bd: float = 1e-12, want_orth_loss=False,
+              mu: float = None):
+    """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4)."""
+    n = op.n
+    B = np.asarray(B, dtype=np.float64)
+    if not np.all(np.isfinite(B[:, :p + 1])):
+        info = Info()
+        info.status = STATUS_NONFINITE
+        return np.full(n, np.nan), info
+    if mu is None:
+        mu = balance_scale(B, p)
+    w = start_vector(B, p, mu)
+    if h == 0.0:
+        return B[:, 0].copy(), Info()
+
+    def apply(x):
+        return aug_apply(op, B, p, mu, x)
+
+    r, info = expmv(apply, w, h, tol=tol, m_max=m_max, fixed_m=fixed_m,
+                    fixed_substeps=fixed_substeps, orth=orth, tform=tform,
+                    max_substeps=max_substeps, delta=delta, eps_bd=eps_bd,
+                    want_orth_loss=want_orth_loss)
+    return r[:n].copy(), info

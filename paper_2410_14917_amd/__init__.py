@@ -129,6 +129,27 @@ class Context:
         _lib.check(rc, self.h)
         return (out, inf.as_dict()) if info else out
 
+    def phi_combo_tangent(self, op: Operator, dop: Operator, B, h: float, tol: float = 1e-8,
+                          m_max: int = 64, out=None, dout=None, info: bool = False):
+        """(out, dout): the phi combination and its derivative along the
+        operator direction dop (same kind and grid as op; its nu, ax, ay,
+        react are the direction).  One Krylov solve of the block operator."""
+        torch = _torch()
+        n = op.n
+        p, ldb = self._check_B(B, n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=B.device)
+        if dout is None:
+            dout = torch.empty(n, dtype=torch.float64, device=B.device)
+        opc, dopc = op.c_struct(), dop.c_struct()
+        inf = KpInfo() if info else None
+        rc = self.lib.kp_phi_combo_tangent(
+            self.h, ctypes.byref(opc), ctypes.byref(dopc), ctypes.c_void_p(B.data_ptr()), p, ldb,
+            float(h), float(tol), int(m_max), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(dout.data_ptr()), ctypes.byref(inf) if inf is not None else None)
+        _lib.check(rc, self.h)
+        return (out, dout, inf.as_dict()) if info else (out, dout)
+
     def schedule(self, cap: int = 8192):
         import numpy as np
         tau = np.zeros(cap)

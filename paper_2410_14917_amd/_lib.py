@@ -24,7 +24,8 @@ ORTH = {"h-gsmgs": KP_ORTH_H_GSMGS, "h-cwy": KP_ORTH_H_CWY, "h-ncwy": KP_ORTH_H_
 BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
 
 # Exported symbols (every function declared in the header).
-SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_get_schedule",
+SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_tangent",
+           "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
            "kp_strerror", "kp_last_error", "kp_version")
 
@@ -78,6 +79,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_set_config.argtypes = [P, ctypes.POINTER(KpConfig)]
     lib.kp_phi_combo.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, D, D, I32, P,
                                  ctypes.POINTER(KpInfo)]
+    lib.kp_phi_combo_tangent.argtypes = [P, ctypes.POINTER(KpOp), ctypes.POINTER(KpOp), P, I32,
+                                         I64, D, D, I32, P, P, ctypes.POINTER(KpInfo)]
     lib.kp_get_schedule.argtypes = [P, P, P, I32]
     lib.kp_arnoldi_begin.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, I32]
     lib.kp_arnoldi_step.argtypes = [P, I32]

@@ -100,7 +100,10 @@ struct State {
 // Internal vector layout (length ld): plane s (s < nplanes) at s*npt_pad,
 // row-major nx x ny inside the plane; the augmented tail (p entries) at
 // tail_off; zero padding elsewhere.  The caller's B, fields and out use the
-// plain layout (plane s at s*npt).
+// plain layout (plane s at s*npt).  In tangent mode the vector is the pair
+// [a; c] of two augmented vectors of a one-plane operator: plane 0 = a_top,
+// plane 1 = c_top, tail = [a_tail (pb entries); c_tail (pb entries)]; both
+// planes read B and the fields at the plain in-plane index.
 struct Args {
   void* V;            // basis, ld x (m_max + 2), element type per basis_f32
   double* u;          // substep state vector, float64, length ld
@@ -109,6 +112,7 @@ struct Args {
   const double* f0;
   const double* f1;
   double* out;
+  double* dout;       // tangent mode: the directional derivative (plane 0)
   double* part;       // [nwg][kKStride] partial sums        (coherent)
   unsigned* sync;     // [0] arrivals, [1] releases, [2] abort (coherent)
   State* st;          // workgroup 0 only
@@ -118,10 +122,13 @@ struct Args {
   double* tx;         // tail values [kTailPad]               (coherent)
   unsigned* flags;    // per-workgroup production counters, kFlagStride apart
   int64_t ld, npt_pad, tail_off;
-  int N, p, npt, nx, ny, nplanes;
+  int N, p, npt, nx, ny, nplanes;   // p: tail length (2 pb in tangent mode)
+  int pb;             // number of phi terms beyond b_0 (columns b_1..b_pb of B)
+  int tangent;        // 1: Van Loan block operator [[Atilde, dAtilde], [0, Atilde]]
   int nwg, rows_per_wg;
   int kind, transpose;
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
+  double dcx, dcy, dadx, dady, dreact;   // tangent mode: the direction dA
   int orth, fixed_m, fixed_substeps, max_substeps, m_max;
   int stop_j;         // pause when this many steps are completed (INT_MAX: never)
   int basis_f32;

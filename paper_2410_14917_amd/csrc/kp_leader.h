@@ -57,13 +57,13 @@ __device__ __attribute__((always_inline)) inline void leader_stage(const Args& a
   const double mx = block_max(m0, red);
   const double bad = block_max(m1, red);
   double mu = 1.0;
-  if (a.p > 0 && mx > 0.0 && isfinite(mx)) {
+  if (a.pb > 0 && mx > 0.0 && isfinite(mx)) {
     int e;
     frexp(mx, &e);
     mu = ldexp(1.0, e - 1);            // largest power of two <= max |b_k|
   }
   for (int k = kp_tid(); k < kTailPad; k += kThreads) {
-    const double v = (a.p > 0 && k == a.p - 1) ? mu : 0.0;
+    const double v = (a.pb > 0 && k == a.p - 1) ? mu : 0.0;   // e_p of the (c) tail
     a.u[a.tail_off + k] = v;
     cstore(a.tx + k, v);
   }

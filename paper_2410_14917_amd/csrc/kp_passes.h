@@ -121,6 +121,25 @@ __device__ inline Seg seg_at(const Args& a, const Rows& o, int si) {
   return Seg{base + (int64_t)o.r0 * a.nx, base + (int64_t)o.r1 * a.nx, si};
 }
 
+// Offset of plane s in the caller's arrays (B, fields): the plain layout puts
+// plane s at s*npt; in tangent mode both planes belong to one plane of the
+// operator.
+__device__ inline int64_t ext_off(const Args& a, int s) {
+  return a.tangent ? 0 : (int64_t)s * a.npt;
+}
+
+// Output array of plane s (indexed by the in-plane index).
+__device__ inline double* out_plane(const Args& a, int s) {
+  if (a.tangent) return s == 0 ? a.dout : a.out;
+  return a.out + (int64_t)s * a.npt;
+}
+
+// The tail shift K acts within each block of pb entries (two blocks in
+// tangent mode): entry k takes entry k+1 unless k closes its block.
+__device__ inline bool tail_shift_in(const Args& a, int k) {
+  return k + 1 < a.p && ((k + 1) % a.pb) != 0;
+}
+
 constexpr int kR = 4;    // element pairs per thread per sub-tile
 constexpr int kCh = 2;   // basis columns per chunk of the inner-product loop
 constexpr int kCu = 8;   // basis columns per chunk of the linear combinations
@@ -248,13 +267,39 @@ __device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x,
       xs = rnd<TB>(cload(a.hx + halo_at(a, (int)((unsigned)rs / (unsigned)a.rows_per_wg), s, 1, ix)));
     }
   }
-  const double cxx = s ? a.cx2 : a.cx, cyy = s ? a.cy2 : a.cy;
+  const double cxx = (s && !a.tangent) ? a.cx2 : a.cx, cyy = (s && !a.tangent) ? a.cy2 : a.cy;
   const double lap = cxx * (xe + xw - 2.0 * c) + cyy * (xn + xs - 2.0 * c);
+  double tv = 0.0;
+  if (a.tangent && s == 0) {
+    // dA applied to the c half (plane 1) at the same point (Van Loan block)
+    const int64_t o = a.npt_pad;
+    const double c1 = xo;
+    const double e1 = x((valid ? ie : e) + o), w1 = x((valid ? iw : e) + o);
+    double n1 = x(in + o), s1 = x(is + o);
+    if (HL) {
+      const double hn1 = hl[1 * nx + ix];
+      const double hs1 = hl[(a.nplanes + 1) * nx + ix];
+      n1 = hn ? n1 : hn1;
+      s1 = hs ? s1 : hs1;
+    } else {
+      if (!hn) {
+        const int rn = (row + 1 == a.ny) ? 0 : row + 1;
+        n1 = rnd<TB>(cload(a.hx + halo_at(a, (int)((unsigned)rn / (unsigned)a.rows_per_wg), 1, 0, ix)));
+      }
+      if (!hs) {
+        const int rs = (row == 0) ? a.ny - 1 : row - 1;
+        s1 = rnd<TB>(cload(a.hx + halo_at(a, (int)((unsigned)rs / (unsigned)a.rows_per_wg), 1, 1, ix)));
+      }
+    }
+    const double dadv = a.dadx * (e1 - w1) + a.dady * (n1 - s1);
+    tv = a.dcx * (e1 + w1 - 2.0 * c1) + a.dcy * (n1 + s1 - 2.0 * c1) +
+         (a.transpose ? dadv : -dadv) + a.dreact * c1;
+  }
   if (a.kind == KP_OP_ADR) {
     const double adv = a.adx * (xe - xw) + a.ady * (xn - xs);
-    return lap + (a.transpose ? adv : -adv) + (a.react + U) * c;
+    return lap + (a.transpose ? adv : -adv) + (a.react + U) * c + tv;
   }
-  if (a.kind == KP_OP_ALLEN_CAHN) return lap + (1.0 - 3.0 * U * U) * c;
+  if (a.kind == KP_OP_ALLEN_CAHN) return lap + (1.0 - 3.0 * U * U) * c + tv;
   // Brusselator Jacobian: pointwise blocks [[a11, a12], [a21, a22]]; the other
   // species at the same point (xo) is owned by this workgroup too.
   const double a11 = 2.0 * U * W - (a.bb + 1.0), a12 = U * U;
@@ -271,15 +316,15 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
                                 const double* hl, int64_t t0, const uint32_t* lo,
                                 const double* tc, double2* w) {
   const int64_t base = (int64_t)sg.plane * a.npt_pad;
-  const int64_t xoff = (int64_t)sg.plane * a.npt;   // external plane offset
+  const int64_t xoff = ext_off(a, sg.plane);         // offset in the caller's arrays
   // B-hat x_tail / mu: the columns b_{p-c}, two at a time with all their
   // loads issued before the first use (the first two go out with the
   // stencil's loads)
   double b0[2][kR][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (c < a.p) {
-      const int64_t col = (int64_t)(a.p - c) * a.ldb + xoff - base;
+    if (c < a.pb) {
+      const int64_t col = (int64_t)(a.pb - c) * a.ldb + xoff - base;
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const int64_t e = t0 + lo[r];
@@ -299,7 +344,7 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (c < a.p) {
+    if (c < a.pb) {
       const double t = tc[c];
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
@@ -309,12 +354,12 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
       }
     }
   }
-  for (int c0 = 2; c0 < a.p; c0 += 2) {
+  for (int c0 = 2; c0 < a.pb; c0 += 2) {
     double bv[2][kR][2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      if (c0 + c < a.p) {
-        const int64_t col = (int64_t)(a.p - c0 - c) * a.ldb + xoff - base;
+      if (c0 + c < a.pb) {
+        const int64_t col = (int64_t)(a.pb - c0 - c) * a.ldb + xoff - base;
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
           const int64_t e = t0 + lo[r];
@@ -325,7 +370,7 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      if (c0 + c < a.p) {
+      if (c0 + c < a.pb) {
         const double t = tc[c0 + c];
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
@@ -343,8 +388,8 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
 // wave 0 takes basis column i (and i + 64), so the work is one memory round
 // trip and at most kPMax wave reductions.
 
-// Tail rows of the matvec of step jj (w_tail = K x_tail, the upward shift;
-// x_tail is also stored at the first step) and their share of the inner
+// Tail rows of the matvec of step jj (w_tail = K x_tail, the upward shift
+// within each block of pb entries; x_tail is also stored at the first step) and their share of the inner
 // products: x_i . x and x_i . w (slots 2i, 2i+1 of wave 0's row of sacc) and
 // x . x, x . w, w . w (slots 2jj .. 2jj+2).
 template <typename TB>
@@ -360,9 +405,9 @@ __device__ inline void tail_matvec_dots(const Args& a, int jj, const Src<TB>& x,
 #pragma unroll
   for (int k = 0; k < kPMax; ++k) xt[k] = (k < p) ? x(T0 + k) : 0.0;
 #pragma unroll
-  for (int k = 0; k < kPMax; ++k) wt[k] = (k + 1 < kPMax && k + 1 < p) ? xt[k + 1] : 0.0;
+  for (int k = 0; k < kPMax; ++k) wt[k] = (k + 1 < kPMax && tail_shift_in(a, k)) ? xt[k + 1] : 0.0;
   if (t < p) {
-    wcol[T0 + t] = (TB)((t + 1 < p) ? x(T0 + t + 1) : 0.0);
+    wcol[T0 + t] = (TB)(tail_shift_in(a, t) ? x(T0 + t + 1) : 0.0);
     if (jj == 0) xcol[T0 + t] = (TB)x(T0 + t);
   }
   if (t < jj) {
@@ -433,6 +478,7 @@ __device__ inline double tail_combine_cols(const Args& a, const TB* V, int nc, c
 }
 
 // ---- stage: u = [b_0; 0] (the leader adds mu e_p), max |b_k| for k >= 1 -----
+// (tangent mode: u = [0; b_0], the a half zero.)
 // Partial slots: [0] = max |b_k|, [1] = 1 if a non-finite entry was seen.
 __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, double* red) {
   const Rows o = own_rows(a);
@@ -440,13 +486,15 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
+    const bool zero = a.tangent && sg.plane == 0;
+    const int64_t xoff = ext_off(a, sg.plane) - (int64_t)sg.plane * a.npt_pad;
     for (int64_t e = sg.beg + kp_tid(); e < ((sg.end + 1) & ~(int64_t)1); e += kThreads) {
       double v = 0.0;
-      if (e < sg.end) {
-        const int64_t eext = e - (int64_t)sg.plane * a.npt_pad + (int64_t)sg.plane * a.npt;
+      if (e < sg.end && !zero) {
+        const int64_t eext = e + xoff;
         v = a.B[eext];
         if (!isfinite(v)) bad = 1.0;
-        for (int k = 1; k <= a.p; ++k) {
+        for (int k = 1; k <= a.pb; ++k) {
           const double b = a.B[(int64_t)k * a.ldb + eext];
           if (!isfinite(b)) bad = 1.0;
           mx = fmax(mx, fabs(b));
@@ -519,9 +567,6 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   for (int k = kp_tid(); k < kWaves * kKStride; k += kThreads) sacc[k] = 0.0;
   if (HL) stage_halo<TB>(a, o, hl);
   const double inv_mu = cload(&a.pub->inv_mu);
-  double tc[kPMax];
-#pragma unroll
-  for (int c = 0; c < kPMax; ++c) tc[c] = (c < a.p) ? rnd<TB>(cload(a.tx + c)) * inv_mu : 0.0;
   __syncthreads();
   TB* xcol = V + (int64_t)jj * ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
@@ -531,6 +576,13 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
     const int64_t pend = (sg.end + 1) >> 1;
+    // tail entries divided by mu that multiply b_{pb-c} in this plane (the c
+    // half of the tail in the tangent mode's plane 1)
+    const int toff = (a.tangent && sg.plane == 1) ? a.pb : 0;
+    double tc[kPMax];
+#pragma unroll
+    for (int c = 0; c < kPMax; ++c)
+      tc[c] = (c < a.pb) ? rnd<TB>(cload(a.tx + toff + c)) * inv_mu : 0.0;
     for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
       const int64_t t0 = 2 * q0;
       uint32_t lo[kR];
@@ -655,7 +707,7 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
     const int64_t pend = (sg.end + 1) >> 1;
-    const int64_t shift = (int64_t)sg.plane * (a.npt - a.npt_pad);
+    double* const outp = out_plane(a, sg.plane) - (int64_t)sg.plane * a.npt_pad;
     for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
       const int64_t t0 = 2 * q0;
       uint32_t lo[kR];
@@ -674,8 +726,8 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
           *reinterpret_cast<double2*>(a.u + e) = acc[r];
           if (!last) publish_pair(a, sg, e, acc[r].x, acc[r].y);
           if (last) {
-            if (e < sg.end) a.out[e + shift] = acc[r].x;
-            if (e + 1 < sg.end) a.out[e + 1 + shift] = acc[r].y;
+            if (e < sg.end) outp[e] = acc[r].x;
+            if (e + 1 < sg.end) outp[e + 1] = acc[r].y;
           }
         }
       }
@@ -689,9 +741,9 @@ __device__ __attribute__((always_inline)) inline void finish_pass(const Args& a,
   const Rows o = own_rows(a);
   for (int si = 0; si < a.nplanes; ++si) {
     const Seg sg = seg_at(a, o, si);
-    const int64_t shift = (int64_t)sg.plane * (a.npt - a.npt_pad);
+    double* const outp = out_plane(a, sg.plane) - (int64_t)sg.plane * a.npt_pad;
     for (int64_t e = sg.beg + kp_tid(); e < sg.end; e += kThreads)
-      a.out[e + shift] = nonfinite ? __builtin_nan("") : a.u[e];
+      outp[e] = nonfinite ? __builtin_nan("") : a.u[e];
   }
 }
 

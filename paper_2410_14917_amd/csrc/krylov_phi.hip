@@ -309,6 +309,9 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.out = out;
   r.N = (int)N;
   r.p = p;
+  r.pb = p;
+  r.tangent = 0;
+  r.dout = nullptr;
   r.npt = (int)npt;
   r.nx = A->nx;
   r.ny = A->ny;
@@ -551,6 +554,50 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_
   Args a;
   int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, out, true, &a);
   if (rc) return rc;
+  if ((rc = prepare(ctx, &a))) return rc;
+  const int m0 = a.fixed_m > 0 ? a.fixed_m : std::min(16, a.m_max);
+  if ((rc = launch_init(ctx, a, m0))) return rc;
+  if ((rc = launch(ctx, a, 0))) return rc;
+  ctx->last = a;
+  ctx->have_begin = 0;
+  if (info) return fill_info(ctx, info);
+  return KP_OK;
+}
+
+int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const double* B,
+                         int32_t p, int64_t ldb, double h, double tol, int32_t m_max,
+                         double* out, double* dout, kp_info* info) {
+  if (!ctx || !A || !dA || !dout) return KP_EINVAL;
+  if (A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) return KP_EUNSUPPORTED;
+  if (dA->kind != A->kind || dA->nx != A->nx || dA->ny != A->ny || dA->dx != A->dx ||
+      dA->dy != A->dy || (dA->transpose != 0) != (A->transpose != 0))
+    return KP_EINVAL;
+  if (dA->field0 || dA->field1) return KP_EUNSUPPORTED;
+  const double dc[] = {dA->nu, dA->ax, dA->ay, dA->react};
+  for (double v : dc)
+    if (!std::isfinite(v)) return KP_EINVAL;
+  if (p < 0 || 2 * p > KP_PMAX) return KP_EUNSUPPORTED;
+  Args a;
+  int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, out, true, &a);
+  if (rc) return rc;
+  const size_t ob = (size_t)a.N * sizeof(double);
+  if (overlaps(dout, ob, out, ob) || overlaps(dout, ob, B, (size_t)ldb * (p + 1) * sizeof(double)) ||
+      overlaps(dout, ob, A->field0, ob))
+    return KP_EINVAL;
+  // the pair [a; c] of augmented vectors: two planes, tail of 2p entries
+  a.tangent = 1;
+  a.dout = dout;
+  a.nplanes = 2;
+  a.pb = p;
+  a.p = 2 * p;
+  a.tail_off = a.npt_pad * 2;
+  a.ld = a.tail_off + kp::kTailPad;
+  a.halo_lds = (2 * 2 * (int64_t)A->nx <= kp::kHaloCap) ? 1 : 0;
+  a.dcx = dA->nu / (A->dx * A->dx);
+  a.dcy = dA->nu / (A->dy * A->dy);
+  a.dadx = dA->ax / (2.0 * A->dx);
+  a.dady = dA->ay / (2.0 * A->dy);
+  a.dreact = dA->react;
   if ((rc = prepare(ctx, &a))) return rc;
   const int m0 = a.fixed_m > 0 ? a.fixed_m : std::min(16, a.m_max);
   if ((rc = launch_init(ctx, a, m0))) return rc;

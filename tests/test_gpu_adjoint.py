@@ -1,0 +1,256 @@
+"""Parity of the derivative entry point (kp_phi_combo_tangent) and of the
+torch.autograd gradients with the oracle's derivatives (oracle/adjoint.py,
+oracle/closed_form.py) and with central differences of the library itself."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint, closed_form, krylov
+import paper_2410_14917_amd as kp
+from paper_2410_14917_amd import autograd as kpa
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def dev_B(Bh):
+    return torch.as_tensor(np.ascontiguousarray(Bh.T), device="cuda")
+
+
+def host_dir(op, nu, ax, ay, react):
+    """The oracle's direction: the constant-coefficient stencil dA."""
+    return dataclasses.replace(op, kind=W.OP_ADR, field0=None, field1=None, nu=nu, ax=ax,
+                               ay=ay, react=react)
+
+
+def dev_dir(op, nu, ax, ay, react):
+    """The library's direction: same kind, grid and transpose flag as op."""
+    return kp.Operator(op.kind, op.nx, op.ny, nu=nu, ax=ax, ay=ay, react=react,
+                       transpose=op.transpose, dx=op.dx, dy=op.dy)
+
+
+# ---- tangent, fixed schedule, against the oracle's block-operator Krylov -----
+
+TAN_FIXED = [
+    # kind, nx, ny, p, m, nsub, transpose
+    (W.OP_ADR, 64, 48, 2, 32, 2, False),
+    (W.OP_ADR, 45, 33, 0, 20, 1, False),
+    (W.OP_ADR, 50, 37, 3, 24, 3, True),
+    (W.OP_ALLEN_CAHN, 80, 72, 2, 32, 2, False),
+    (W.OP_ADR, 128, 100, 4, 40, 1, False),
+]
+DIRECTION = (0.7, 0.3, -0.2, 1.1)
+
+
+@pytest.mark.parametrize("case", TAN_FIXED)
+@pytest.mark.parametrize("orth", [("h-gsmgs", "gsmgs"), ("h-cwy", "cwy")])
+def test_tangent_fixed_schedule(case, orth):
+    kind, nx, ny, p, m, nsub, tr = case
+    say(f"tangent fixed kind={kind} {nx}x{ny} p={p} m={m} nsub={nsub} T={tr} {orth[0]}")
+    pr = W.random_problem(41, kind=kind, nx=nx, ny=ny, p=p, h=0.05, with_diag=True)
+    oph = pr.op.with_transpose() if tr else pr.op
+    op = kp.Operator.from_host(oph)
+    with kp.Context(orth=orth[0], fixed_m=m, fixed_substeps=nsub) as ctx:
+        y, dy, info = ctx.phi_combo_tangent(op, dev_dir(op, *DIRECTION), dev_B(pr.B), pr.h,
+                                            m_max=m, info=True)
+        y0 = ctx.phi_combo(op, dev_B(pr.B), pr.h, m_max=m)
+    ry, rdy, rinfo = adjoint.phi_combo_tangent(oph, host_dir(oph, *DIRECTION), pr.B, pr.h, p,
+                                               fixed_m=m, fixed_substeps=nsub, m_max=m,
+                                               orth="hybrid", tform=orth[1])
+    e_y, e_dy = rel(y.cpu().numpy(), ry), rel(dy.cpu().numpy(), rdy)
+    say(f"  rel y {e_y:.2e} dy {e_dy:.2e}")
+    assert info["status"] == 0 and info["substeps"] == nsub
+    assert info["arnoldi_steps"] == rinfo.arnoldi_steps
+    assert e_y <= FP64_TOL and e_dy <= FP64_TOL
+    # the y half is the plain phi combination (a different Krylov space, so
+    # equal only to the accuracy of both projections)
+    assert rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-6
+
+
+# ---- tangent, adaptive ------------------------------------------------------
+
+def test_tangent_adaptive_matches_oracle_and_closed_form():
+    # 6-7 substeps with 4-5 rejected steps on the oracle: the controller is
+    # exercised.  Its decisions are compared at tol 1e-8: at 1e-10 the error
+    # estimate (the last entry of exp(tau Hbar) e_1) is near the rounding
+    # level of the Arnoldi process on the doubled vector, and the oracle's own
+    # MGS, H-GSMGS and H-CWY runs already pick step sizes a few percent apart
+    # from the fifth substep on (with results equal to 1e-12); at 1e-8 they
+    # agree to ~1e-5 of h.  The closed-form check runs at 1e-10.
+    op_h = W.Operator(kind=W.OP_ADR, nx=96, ny=80, nu=0.05, ax=1.0, ay=0.5, react=-0.3)
+    rng = np.random.default_rng(43)
+    Bh = rng.standard_normal((op_h.n, 3))
+    h, p = 0.1, 2
+    op = kp.Operator.from_host(op_h)
+    dA, dAh = dev_dir(op, 1.0, 0, 0, 0), host_dir(op_h, 1.0, 0, 0, 0)
+    with kp.Context() as ctx:
+        y, dy, info = ctx.phi_combo_tangent(op, dA, dev_B(Bh), h, tol=1e-8, m_max=32,
+                                            info=True)
+        sched = ctx.schedule()
+        y10, dy10, info10 = ctx.phi_combo_tangent(op, dA, dev_B(Bh), h, tol=1e-10, m_max=32,
+                                                  info=True)
+    ry, rdy, rinfo = adjoint.phi_combo_tangent(op_h, dAh, Bh, h, p, tol=1e-8, m_max=32,
+                                               orth="hybrid")
+    y, dy, y10, dy10 = (t.cpu().numpy() for t in (y, dy, y10, dy10))
+    say(f"  substeps gpu {info['substeps']} oracle {rinfo.substeps}; "
+        f"rel y {rel(y, ry):.2e} dy {rel(dy, rdy):.2e}")
+    assert info["status"] == 0 and info["t_end"] == h
+    assert rinfo.substeps >= 4 and info["rejected"] == rinfo.rejected
+    assert [s[1] for s in sched] == [s[1] for s in rinfo.schedule]
+    assert np.allclose([s[0] for s in sched], [s[0] for s in rinfo.schedule], rtol=0,
+                       atol=1e-5 * h)
+    assert rel(y, ry) <= FP64_TOL and rel(dy, rdy) <= FP64_TOL
+    y_cf, dy_cf = closed_form.adr_phi_combo(op_h, Bh, h, p), closed_form.adr_phi_combo_dnu(
+        op_h, Bh, h, p)
+    say(f"  tol 1e-10: substeps {info10['substeps']} rel y {rel(y10, y_cf):.2e} "
+        f"dy {rel(dy10, dy_cf):.2e} vs closed form")
+    assert info10["status"] == 0 and info10["t_end"] == h
+    assert rel(y10, y_cf) <= 1e-9
+    assert rel(dy10, dy_cf) <= 1e-8
+
+
+def test_tangent_h_zero_and_zero_direction():
+    pr = W.random_problem(44, nx=40, ny=30, p=2)
+    op = kp.Operator.from_host(pr.op)
+    B = dev_B(pr.B)
+    with kp.Context() as ctx:
+        y, dy = ctx.phi_combo_tangent(op, dev_dir(op, 1.0, 0, 0, 0), B, 0.0)
+        assert np.array_equal(y.cpu().numpy(), pr.B[:, 0])
+        assert not dy.abs().any()
+        y, dy = ctx.phi_combo_tangent(op, dev_dir(op, 0, 0, 0, 0), B, pr.h, tol=1e-10)
+        y0 = ctx.phi_combo(op, B, pr.h, tol=1e-10)
+    assert not dy.abs().any()
+    assert rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-8
+
+
+def test_tangent_rejects_unsupported_and_mismatched():
+    pr = W.random_problem(45, nx=32, ny=24, p=2)
+    op = kp.Operator.from_host(pr.op)
+    B = dev_B(pr.B)
+    with kp.Context() as ctx:
+        with pytest.raises(RuntimeError, match=r"\[-1\]"):      # grid differs
+            ctx.phi_combo_tangent(op, kp.Operator(op.kind, op.nx + 1, op.ny, nu=1.0), B, 0.1)
+        with pytest.raises(RuntimeError, match=r"\[-1\]"):      # transpose differs
+            ctx.phi_combo_tangent(op, kp.Operator(op.kind, op.nx, op.ny, nu=1.0,
+                                                  transpose=True), B, 0.1)
+        with pytest.raises(RuntimeError, match=r"\[-4\]"):      # direction with a field
+            d = kp.Operator(op.kind, op.nx, op.ny, nu=1.0,
+                            field0=torch.zeros(op.n, dtype=torch.float64, device="cuda"))
+            ctx.phi_combo_tangent(op, d, B, 0.1)
+        prb = W.random_problem(46, kind=W.OP_BRUSSELATOR, nx=16, ny=16, p=1)
+        opb = kp.Operator.from_host(prb.op)
+        with pytest.raises(RuntimeError, match=r"\[-4\]"):      # Brusselator: no tangent
+            ctx.phi_combo_tangent(opb, kp.Operator(opb.kind, 16, 16, nu=1.0), dev_B(prb.B),
+                                  0.1)
+
+
+# ---- autograd ---------------------------------------------------------------
+
+def test_autograd_gradients_match_closed_form_and_differences():
+    op_h = W.Operator(kind=W.OP_ADR, nx=64, ny=48, nu=0.02, ax=1.0, ay=-0.5, react=-0.2)
+    rng = np.random.default_rng(47)
+    Bh = rng.standard_normal((op_h.n, 3))
+    wh = rng.standard_normal(op_h.n)
+    h, p, tol = 0.05, 2, 1e-12
+    op = kp.Operator.from_host(op_h)
+    B = dev_B(Bh).requires_grad_(True)
+    nu = torch.tensor(op_h.nu, dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.as_tensor(wh, device="cuda")
+    y = kpa.phi_combo(B, nu, op, h, tol=tol, m_max=48)
+    (w @ y).backward()
+    gB, gnu = B.grad.cpu().numpy().T, float(nu.grad)
+    # closed forms: dL/db_k = h^k phi_k(h A^T) w, dL/dnu = <w, dy/dnu>
+    gB_ref = adjoint.grad_B(op_h, wh, h, p, closed_form.adr_phi_combo)
+    gnu_ref = float(wh @ closed_form.adr_phi_combo_dnu(op_h, Bh, h, p))
+    say(f"  grad_B rel {rel(gB, gB_ref):.2e}  grad_nu {gnu:.12e} ref {gnu_ref:.12e}")
+    assert rel(gB, gB_ref) <= 1e-9
+    assert abs(gnu - gnu_ref) <= 1e-8 * abs(gnu_ref)
+    # central differences of the library's own forward map, on a fixed
+    # schedule (48 steps, 4 substeps: converged far below the differences'
+    # resolution; the adaptive controller's decisions move with nu and put
+    # noise of order tol / eps into a difference quotient).  In nu the third
+    # derivative is large (the stiff modes carry powers of h * lambda), so
+    # the quotient is Richardson-extrapolated: (4 D(e/2) - D(e)) / 3 cancels
+    # the e^2 term.  The map is linear in B: one plain quotient suffices.
+    fx = dict(fixed_m=48, fixed_substeps=4)
+
+    def f(Bv, nuv):
+        return float(w @ kpa.phi_combo(Bv, nuv, op, h, m_max=48, **fx))
+
+    with torch.no_grad():
+        e = 2e-6
+        d1 = (f(B, nu + e) - f(B, nu - e)) / (2 * e)
+        d2 = (f(B, nu + e / 2) - f(B, nu - e / 2)) / e
+        fd_nu = (4 * d2 - d1) / 3
+        v = torch.as_tensor(rng.standard_normal((p + 1, op_h.n)), device="cuda")
+        fd_v = (f(B + 1e-5 * v, nu) - f(B - 1e-5 * v, nu)) / 2e-5
+    dir_v = float((B.grad * v).sum())
+    say(f"  fd nu {fd_nu:.10e} vs {gnu:.10e}; fd v {fd_v:.10e} vs {dir_v:.10e}")
+    assert abs(fd_nu - gnu) <= 1e-7 * abs(gnu)
+    assert abs(fd_v - dir_v) <= 1e-8 * abs(dir_v)
+
+
+def test_autograd_allen_cahn_matches_oracle():
+    """Both gradients through an Allen-Cahn Jacobian (a kind that carries a
+    pointwise field) against the oracle's Krylov gradient and tangent."""
+    pr = W.random_problem(48, kind=W.OP_ALLEN_CAHN, nx=72, ny=64, p=2, h=0.05)
+    op = kp.Operator.from_host(pr.op)
+    rng = np.random.default_rng(49)
+    wh = rng.standard_normal(pr.op.n)
+    B = dev_B(pr.B).requires_grad_(True)
+    nu = torch.tensor(pr.op.nu, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = kpa.phi_combo(B, nu, op, pr.h, tol=1e-12, m_max=48)
+    (torch.as_tensor(wh, device="cuda") @ y).backward()
+    gB = B.grad.cpu().numpy().T
+    gB_ref = adjoint.grad_B(pr.op, wh, pr.h, 2, krylov.phi_combo, tol=1e-12, m_max=48,
+                            orth="hybrid")
+    _, rdy, _ = adjoint.phi_combo_tangent(pr.op, host_dir(pr.op, 1.0, 0, 0, 0), pr.B, pr.h, 2,
+                                          tol=1e-12, m_max=48, orth="hybrid")
+    gnu_ref = float(wh @ rdy)
+    say(f"  AC grad_B rel {rel(gB, gB_ref):.2e} grad_nu {float(nu.grad):.12e} "
+        f"ref {gnu_ref:.12e}")
+    assert rel(gB, gB_ref) <= 1e-9
+    assert abs(float(nu.grad) - gnu_ref) <= 1e-8 * abs(gnu_ref)
+
+
+def test_full_size_adjoint_workload():
+    """The adjoint workload at full size (advection-diffusion 1024^2, p = 2,
+    loss ||phi_combo - y||^2, tol 1e-10): both gradients against the DFT
+    closed forms, every element."""
+    pr = W.config5()
+    say("full-size adjoint: GPU")
+    op = kp.Operator.from_host(pr.op)
+    B = dev_B(pr.B).requires_grad_(True)
+    nu = torch.tensor(pr.op.nu, dtype=torch.float64, device="cuda", requires_grad=True)
+    yt = torch.as_tensor(pr.y, device="cuda")
+    yh = kpa.phi_combo(B, nu, op, pr.h, tol=pr.tol, m_max=pr.m_max)
+    loss = ((yh - yt) ** 2).sum()
+    loss.backward()
+    gB, gnu = B.grad.cpu().numpy().T, float(nu.grad)
+    say("full-size adjoint: closed forms")
+    y_ref = closed_form.adr_phi_combo(pr.op, pr.B, pr.h, pr.p)
+    g = 2.0 * (y_ref - pr.y)
+    gB_ref = adjoint.grad_B(pr.op, g, pr.h, pr.p, closed_form.adr_phi_combo)
+    gnu_ref = float(g @ closed_form.adr_phi_combo_dnu(pr.op, pr.B, pr.h, pr.p))
+    e_y = rel(yh.detach().cpu().numpy(), y_ref)
+    e_B = [rel(gB[:, k], gB_ref[:, k]) for k in range(pr.p + 1)]     # per column
+    say(f"  rel y {e_y:.2e} grad_B {[f'{e:.2e}' for e in e_B]} grad_nu {gnu:.12e} "
+        f"ref {gnu_ref:.12e}")
+    assert e_y <= 10 * pr.tol
+    assert max(e_B) <= 1e-8
+    assert abs(gnu - gnu_ref) <= 1e-7 * abs(gnu_ref)
