@@ -183,6 +183,59 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
                          int32_t p, int64_t ldb, double h, double tol, int32_t m_max,
                          double* out, double* dout, kp_info* info);
 
+/*
+ * Many independent phi combinations in one call (the uneven-batch form):
+ *     out[i][0..N_i) = sum_{k=0}^{p_i} h_i^k phi_k(h_i A_i) b_{i,k},  i < nprob,
+ * each computed exactly as kp_phi_combo computes it (Section 3's hybrid
+ * low-synchronisation Arnoldi, Section 2.1's augmented matrix, the adaptive
+ * substeps of the KIOPS-type controller), with the context's configuration
+ * and the common tol and m_max.
+ *   ops, B, p, ldb, h, out: host arrays of nprob entries; B[i] and out[i] are
+ *          device pointers with the layouts of kp_phi_combo; ops[i].field*
+ *          are device pointers.  Outputs of different problems must not
+ *          overlap.
+ *   infos: optional host array of nprob records; when non-NULL the stream is
+ *          synchronised and filled.  A problem that did not finish reports
+ *          KP_STATUS_ABORTED.
+ * The grid of one cooperative launch is split into teams of workgroups; a
+ * team solves its problems one after another with its own barriers.  Every
+ * problem keeps its own basis and state vector for the launch (device memory
+ * ~ sum_i (N_i + padding) (m_max + 3) elements of the basis type), so that no
+ * cache line written by one workgroup is handed to another during the launch.
+ * The
+ * team sizes and the problem-to-team assignment come from the built-in
+ * planner (see kp_batch_plan), computed when the set of problem shapes
+ * (kind, nx, ny, p per problem, nprob, m_max, configuration) differs from the
+ * previous batched call on this context; the plan, the workspace and a HIP
+ * graph (reset kernel -> batched kernel -> outcome records) are kept and the
+ * graph is replayed while the shapes repeat.  The Args of every call
+ * (pointers, coefficients, h, tol) are copied to the device before the
+ * replay, so they may change between calls.  Asynchronous unless infos is
+ * requested.
+ * Errors: KP_EINVAL, KP_ENOMEM, KP_EHIP.
+ */
+int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops,
+                         const double* const* B, const int32_t* p, const int64_t* ldb,
+                         const double* h, double tol, int32_t m_max,
+                         double* const* out, kp_info* infos);
+
+/*
+ * The planner of kp_phi_combo_batched on its own (host only; no device call,
+ * the operators' field pointers are only tested for NULL).  For a grid of
+ * n_wg workgroups it returns the teams (team_wg0[t], team_size[t],
+ * t < *nteams; arrays of capacity n_wg), the team of every problem
+ * (team_of_problem, nprob entries), the predicted makespan and the predicted
+ * single-workgroup time of all problems (work; may be NULL), in seconds.
+ * Cost model: Arnoldi steps ~ max(16, 8 sqrt(h rho)) with rho a bound of
+ * ||A||; streaming bytes per step ~ 8 N (m + p + c + 6); a serial cost per
+ * step and per small exponential; problems, heaviest first, go to the team
+ * that finishes them earliest, over a search of team-size mixes.
+ * Errors: KP_EINVAL.
+ */
+int kp_batch_plan(int32_t nprob, const kp_op* ops, const int32_t* p, const double* h,
+                  int32_t m_max, int32_t n_wg, int32_t* team_of_problem, int32_t* team_wg0,
+                  int32_t* team_size, int32_t* nteams, double* makespan, double* work);
+
 /* Copy the (tau_i, m_i) of the accepted substeps of the last call into host
  * arrays of capacity cap; returns the number copied (>= 0) or a KP_E code. */
 int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap);

@@ -150,6 +150,35 @@ class Context:
         _lib.check(rc, self.h)
         return (out, dout, inf.as_dict()) if info else (out, dout)
 
+    def phi_combo_batched(self, ops, Bs, hs, tol: float = 1e-8, m_max: int = 64, outs=None,
+                          info: bool = False):
+        """Independent phi combinations in one call: outs[i] = sum_k hs[i]^k
+        phi_k(hs[i] A_i) Bs[i][k] for the operators ops[i] (Bs[i] is (p_i+1, N_i)).
+        One persistent launch (replayed from a HIP graph while the problem
+        shapes repeat).  Returns the list of outputs (and of info dicts)."""
+        torch = _torch()
+        n = len(ops)
+        if n < 1 or len(Bs) != n or len(hs) != n:
+            raise ValueError("ops, Bs and hs must have the same positive length")
+        opc = (KpOp * n)(*[o.c_struct() for o in ops])
+        bp = (ctypes.c_void_p * n)()
+        pp = (ctypes.c_int32 * n)()
+        lb = (ctypes.c_int64 * n)()
+        hh = (ctypes.c_double * n)(*[float(x) for x in hs])
+        if outs is None:
+            outs = [torch.empty(o.n, dtype=torch.float64, device=B.device) for o, B in zip(ops, Bs)]
+        op_ = (ctypes.c_void_p * n)()
+        for i, (o, B, y) in enumerate(zip(ops, Bs, outs)):
+            p, ldb = self._check_B(B, o.n)
+            if y.dtype != torch.float64 or not y.is_cuda or not y.is_contiguous() or y.numel() != o.n:
+                raise ValueError("outs[i] must be a contiguous float64 device vector of N_i")
+            bp[i], pp[i], lb[i], op_[i] = B.data_ptr(), p, ldb, y.data_ptr()
+        inf = (KpInfo * n)() if info else None
+        rc = self.lib.kp_phi_combo_batched(self.h, n, opc, bp, pp, lb, hh, float(tol), int(m_max),
+                                           op_, inf)
+        _lib.check(rc, self.h)
+        return (outs, [r.as_dict() for r in inf]) if info else outs
+
     def schedule(self, cap: int = 8192):
         import numpy as np
         tau = np.zeros(cap)
@@ -202,3 +231,31 @@ def phi_combo(op: Operator, B, h: float, tol: float = 1e-8, m_max: int = 64,
     """One-shot convenience wrapper (creates and frees a Context)."""
     with Context(**ctx_kw) as ctx:
         return ctx.phi_combo(op, B, h, tol=tol, m_max=m_max, info=info)
+
+
+def batch_plan(ops, ps, hs, m_max: int = 64, n_wg: int = 256):
+    """The batched call's planner on the host (no device needed): returns
+    (team_of_problem, teams [(first workgroup, size)], predicted makespan s,
+    predicted one-workgroup time s).  ops may be host operators with numpy
+    fields: only the presence of a field matters."""
+    lib = _lib.load()
+    n = len(ops)
+
+    def cs(o):
+        f0 = ctypes.c_void_p(1) if getattr(o, "field0", None) is not None else None
+        f1 = ctypes.c_void_p(1) if getattr(o, "field1", None) is not None else None
+        return KpOp(int(o.kind), int(o.nx), int(o.ny), int(bool(o.transpose)), float(o.dx),
+                    float(o.dy), float(o.nu), float(o.nu2), float(o.ax), float(o.ay),
+                    float(o.react), float(o.brus_a), float(o.brus_b), f0, f1)
+    opc = (KpOp * n)(*[cs(o) for o in ops])
+    pp = (ctypes.c_int32 * n)(*[int(x) for x in ps])
+    hh = (ctypes.c_double * n)(*[float(x) for x in hs])
+    top = (ctypes.c_int32 * n)()
+    w0 = (ctypes.c_int32 * n_wg)()
+    sz = (ctypes.c_int32 * n_wg)()
+    nt = ctypes.c_int32()
+    ms, wk = ctypes.c_double(), ctypes.c_double()
+    _lib.check(lib.kp_batch_plan(n, opc, pp, hh, int(m_max), int(n_wg), top, w0, sz,
+                                 ctypes.byref(nt), ctypes.byref(ms), ctypes.byref(wk)))
+    teams = [(w0[t], sz[t]) for t in range(nt.value)]
+    return list(top), teams, ms.value, wk.value

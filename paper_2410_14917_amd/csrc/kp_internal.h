@@ -57,8 +57,8 @@ enum Phase : int {
 
 constexpr int kFlagStride = 16;           // unsigned per workgroup flag (64 B)
 
-// Control block published by workgroup 0 after every grid-wide sync and read
-// by every workgroup with coherent loads.
+// Control block published by the leader (rank 0) after every grid-wide sync
+// and read by every workgroup of the problem with coherent loads.
 struct Pub {
   int phase;
   int j;            // completed Arnoldi steps of the current substep
@@ -71,8 +71,8 @@ struct Pub {
   double coef[kMMax + 2];   // coefficients of the pending update / of the combine
 };
 
-// Private state of the call, read and written only by workgroup 0 (and by
-// the host between launches).
+// Private state of the call, read and written only by the leader (and by the
+// host between launches).
 struct State {
   int m_target;       // steps to reach before the small exponential
   int m_cur;          // current Krylov dimension choice of the controller
@@ -115,9 +115,9 @@ struct Args {
   double* dout;       // tangent mode: the directional derivative (plane 0)
   double* part;       // [nwg][kKStride] partial sums        (coherent)
   unsigned* sync;     // [0] arrivals, [1] releases, [2] abort (coherent)
-  State* st;          // workgroup 0 only
+  State* st;          // the leader only
   Pub* pub;           // coherent
-  double* ex;         // small-exponential scratch (workgroup 0)
+  double* ex;         // small-exponential scratch (the leader)
   double* hx;         // halo rows [nwg][nplanes][2][nx]      (coherent)
   double* tx;         // tail values [kTailPad]               (coherent)
   unsigned* flags;    // per-workgroup production counters, kFlagStride apart
@@ -125,7 +125,8 @@ struct Args {
   int N, p, npt, nx, ny, nplanes;   // p: tail length (2 pb in tangent mode)
   int pb;             // number of phi terms beyond b_0 (columns b_1..b_pb of B)
   int tangent;        // 1: Van Loan block operator [[Atilde, dAtilde], [0, Atilde]]
-  int nwg, rows_per_wg;
+  int nwg, rows_per_wg;   // workgroups that own rows; rows per workgroup
+  int nteam, wg0;     // workgroups meeting at the barriers (>= nwg), first one's blockIdx
   int kind, transpose;
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
   double dcx, dcy, dadx, dady, dreact;   // tangent mode: the direction dA
@@ -137,6 +138,10 @@ struct Args {
   double h, tol, delta, eps_bd;
   int64_t wait_ticks; // bound of a grid-wide wait, steady-counter ticks
 };
+
+// Rank of this workgroup in the set that solves the problem (the whole grid
+// for a single call, a team of the grid for a batched call).  Rank 0 leads.
+__device__ inline int wg_rank(const Args& a) { return (int)blockIdx.x - a.wg0; }
 
 // ---- coherent (agent-scope) accesses ---------------------------------------
 
@@ -215,7 +220,8 @@ __device__ inline double block_max(double v, double* red) {
 // opens in the low half), abort flag (u32 word 4).
 //
 // Barrier number k (counted identically by every workgroup): every workgroup
-// increments the arrival counter; workgroup 0 waits until it reads k * nwg,
+// increments the arrival counter; the leader (rank 0) waits until it reads
+// k * nteam,
 // does the serial work of the phase, and stores the release word (k, control);
 // the others wait until they read k and take the control of the next phase
 // from the same word.  Each wait is bounded by a.wait_ticks of the steady
@@ -284,14 +290,14 @@ __device__ inline void bar_arrive(const Args& a) {
     __hip_atomic_fetch_add(a.sync + kSyncArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup 0: wait for every arrival at barrier k.  *ok (LDS) = false when
+// Leader: wait for every arrival at barrier k.  *ok (LDS) = false when
 // the launch is aborting.
 __device__ inline void bar_gather(const Args& a, unsigned k, int* ok) {
-  if (kp_tid() == 0) *ok = spin_until(a, a.sync + kSyncArrive, k * (unsigned)a.nwg) ? 1 : 0;
+  if (kp_tid() == 0) *ok = spin_until(a, a.sync + kSyncArrive, k * (unsigned)a.nteam) ? 1 : 0;
   __syncthreads();
 }
 
-// Workgroup 0: open barrier k, announcing the control of the next phase,
+// Leader: open barrier k, announcing the control of the next phase,
 // after its coherent stores completed.  The control is mirrored in the Pub
 // block for the host.
 __device__ inline void bar_release(const Args& a, unsigned k, const Ctl& nxt, Pub* pb) {
@@ -338,14 +344,14 @@ __device__ inline void bar_wait(const Args& a, unsigned k, Ctl* cur, int* ok) {
 __device__ inline void flag_publish(const Args& a, unsigned k) {
   wait_all_stores();
   __syncthreads();
-  if (kp_tid() == 0) cstore(a.flags + (int64_t)blockIdx.x * kFlagStride, k);
+  if (kp_tid() == 0) cstore(a.flags + (int64_t)wg_rank(a) * kFlagStride, k);
 }
 
 // Wait until the two row neighbours (halo) and workgroup 0 (tail) have
 // published the vector of barrier k (the three flags are polled together).
 __device__ inline void flag_wait_neighbours(const Args& a, unsigned k) {
   if (kp_tid() == 0) {
-    const int b = (int)blockIdx.x, nw = a.nwg;
+    const int b = wg_rank(a), nw = a.nwg;
     const unsigned* fp = a.flags + (int64_t)((b == 0) ? nw - 1 : b - 1) * kFlagStride;
     const unsigned* fn = a.flags + (int64_t)((b + 1 == nw) ? 0 : b + 1) * kFlagStride;
     const unsigned* f0 = a.flags;

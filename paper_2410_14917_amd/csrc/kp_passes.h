@@ -103,7 +103,7 @@ struct Rows {
 
 __device__ inline Rows own_rows(const Args& a) {
   Rows o;
-  o.r0 = (int)blockIdx.x * a.rows_per_wg;
+  o.r0 = min(a.ny, wg_rank(a) * a.rows_per_wg);
   o.r1 = min(a.ny, o.r0 + a.rows_per_wg);
   return o;
 }
@@ -196,8 +196,8 @@ __device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix)
 __device__ inline void publish_elem(const Args& a, const Seg& sg, int64_t e, double v) {
   if (e >= sg.end) return;
   const int64_t off = e - sg.beg, last0 = sg.end - sg.beg - a.nx;
-  if (off < a.nx) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 0, (int)off), v);
-  if (off >= last0) cstore(a.hx + halo_at(a, blockIdx.x, sg.plane, 1, (int)(off - last0)), v);
+  if (off < a.nx) cstore(a.hx + halo_at(a, wg_rank(a), sg.plane, 0, (int)off), v);
+  if (off >= last0) cstore(a.hx + halo_at(a, wg_rank(a), sg.plane, 1, (int)(off - last0)), v);
 }
 
 __device__ inline void publish_pair(const Args& a, const Seg& sg, int64_t e, double v0,
@@ -213,7 +213,7 @@ __device__ inline void publish_pair(const Args& a, const Seg& sg, int64_t e, dou
 // hl[s * nx + ix] = row r1 (mod ny), hl[(nplanes + s) * nx + ix] = row r0 - 1.
 template <typename TB>
 __device__ inline void stage_halo(const Args& a, const Rows& o, double* hl) {
-  const int nx = a.nx, b = (int)blockIdx.x;
+  const int nx = a.nx, b = wg_rank(a);
   const int wn = (o.r1 == a.ny) ? 0 : b + 1;
   const int ws = (o.r0 == 0) ? a.nwg - 1 : b - 1;
   for (int s = 0; s < a.nplanes; ++s)
@@ -507,8 +507,8 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
   mx = block_max(mx, red);
   bad = block_max(bad, red);
   if (kp_tid() == 0) {
-    cstore(a.part + (int64_t)blockIdx.x * kKStride + 0, mx);
-    cstore(a.part + (int64_t)blockIdx.x * kKStride + 1, bad);
+    cstore(a.part + (int64_t)wg_rank(a) * kKStride + 0, mx);
+    cstore(a.part + (int64_t)wg_rank(a) * kKStride + 1, bad);
   }
 }
 
@@ -632,13 +632,13 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
     sacc[wv * kKStride + 2 * jj + 1] += sxw;
     sacc[wv * kKStride + 2 * jj + 2] += sww;
   }
-  if (blockIdx.x == 0) tail_matvec_dots<TB>(a, jj, x, V, sacc);
+  if (wg_rank(a) == 0) tail_matvec_dots<TB>(a, jj, x, V, sacc);
   __syncthreads();
   const int nslot = 2 * jj + 3;
   for (int k = kp_tid(); k < nslot; k += kThreads) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += sacc[w * kKStride + k];
-    cstore(a.part + (int64_t)blockIdx.x * kKStride + k, s);
+    cstore(a.part + (int64_t)wg_rank(a) * kKStride + k, s);
   }
 }
 
@@ -687,11 +687,11 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
       }
     }
   }
-  if (blockIdx.x == 0)
+  if (wg_rank(a) == 0)
     ss += tail_combine_cols<TB, TB>(a, V, jj + 1, coef, jj + 1, cw, wcol, true);
   if (want_norm) {
     ss = block_sum(ss, red);
-    if (kp_tid() == 0) cstore(a.part + (int64_t)blockIdx.x * kKStride, ss);
+    if (kp_tid() == 0) cstore(a.part + (int64_t)wg_rank(a) * kKStride, ss);
   }
 }
 
@@ -733,7 +733,7 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
       }
     }
   }
-  if (blockIdx.x == 0) tail_combine_cols<TB, double>(a, V, m, coef, -1, 0.0, a.u, !last);
+  if (wg_rank(a) == 0) tail_combine_cols<TB, double>(a, V, m, coef, -1, 0.0, a.u, !last);
 }
 
 // ---- finish: out = u_top (or NaN when the input was not finite) -------------

@@ -21,6 +21,7 @@
 #include "kp_internal.h"
 #include "kp_leader.h"
 #include "kp_passes.h"
+#include "kp_plan.h"
 
 namespace kp {
 
@@ -59,10 +60,11 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
   double* red = lds + kOffRed;
   double* tv = lds + kOffTv;
   double* hl = lds + kOffHl;
-  const bool lead = blockIdx.x == 0;
+  const bool lead = wg_rank(a) == 0;
   const Ctl c = cur;
-  // streaming part of the phase (every workgroup)
-  switch (c.phase) {
+  // streaming part of the phase (every workgroup that owns rows; the others
+  // of a team larger than the row count only meet the barriers)
+  if (wg_rank(a) < a.nwg) switch (c.phase) {
     case PH_STAGE:
       stage_pass(a, red);
       break;
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
     cur = ctl_unpack((unsigned)w);
     ok = aborted(a) ? 0 : 1;
   }
-  if (blockIdx.x == 0) load_tables(a, lead);
+  if (wg_rank(a) == 0) load_tables(a, lead);
   __syncthreads();
   unsigned k = s_k;
   for (;;) {
@@ -158,8 +160,9 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
 }
 
 // Reset of the call state; the Hessenberg and correction matrices are zeroed
-// so that entries outside their triangles read as zero.
-__global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
+// so that entries outside their triangles read as zero.  Run by one
+// workgroup of any size before the launch that solves the problem.
+__device__ inline void init_problem(const Args& a, int m_target) {
   State* st = a.st;
   for (int i = kp_tid(); i < kLdh * kMMax; i += blockDim.x) st->H[i] = 0.0;
   for (int i = kp_tid(); i < kLdt * kMMax; i += blockDim.x) {
@@ -192,6 +195,105 @@ __global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
   st->err_max = st->omega = st->err = st->last_nrm2 = 0.0;
 }
 
+__global__ __launch_bounds__(256) void k_init(Args a, int m_target) { init_problem(a, m_target); }
+
+// ---- batched call ------------------------------------------------------------
+//
+// Many independent problems in one cooperative launch.  The grid is split into
+// teams of consecutive workgroups (team_of_wg); team t solves the problems
+// order[team_first[t] .. team_first[t+1]) one after another, each exactly as a
+// single call would (its own Args, State, control block and barrier words),
+// so the phases, barriers and coherence rules are those of k_run inside each
+// team.  Every problem also has its own basis and state vector: reusing them
+// for the team's next problem would hand cache lines written with plain
+// stores to other workgroups (other rows, other XCDs) within the launch, and
+// the L2s of different XCDs are not coherent for plain stores.  Only the
+// team's small buffers that are accessed with coherent atomics (partial sums,
+// halo rows, tail values) and the leader's small-exponential scratch (always
+// the same workgroup) are shared by a team's problems; a problem's last
+// barrier (FINISH -> DONE) is passed by every workgroup of the team before
+// any of them touches those for the next problem.
+// The Args records are read through the constant address space: they are not
+// written during the launch and every access has a uniform address, so their
+// fields are fetched with scalar loads, as kernel arguments are.
+typedef __attribute__((address_space(4))) const Args CArgs;
+
+struct BatchDesc {
+  const CArgs* args;       // [nprob], not written during the launch
+  const int* team_first;   // [nteams + 1]
+  const int* order;        // [nprob] problem indices grouped by team
+  const int* team_of_wg;   // [grid] (-1: no work)
+  int nprob;
+};
+
+__device__ inline const Args& batch_args(const CArgs* base, int i) {
+  return *(const Args*)(base + i);
+}
+
+__global__ __launch_bounds__(256) void k_batch_init(BatchDesc d) {
+  const Args& a = batch_args(d.args, (int)blockIdx.x);
+  init_problem(a, a.fixed_m > 0 ? a.fixed_m : min(16, a.m_max));
+}
+
+template <typename TB>
+__global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
+  __shared__ double lds[kLdsDoubles];
+  __shared__ LeadLds lead;
+  __shared__ Ctl cur, nxt;
+  __shared__ int ok;
+  __shared__ unsigned s_k;
+  const int t = __builtin_amdgcn_readfirstlane(d.team_of_wg[blockIdx.x]);
+  if (t < 0) return;
+  const int q1 = __builtin_amdgcn_readfirstlane(d.team_first[t + 1]);
+  for (int q = __builtin_amdgcn_readfirstlane(d.team_first[t]); q < q1; ++q) {
+    const Args& a = batch_args(d.args, __builtin_amdgcn_readfirstlane(d.order[q]));
+    if (kp_tid() == 0) {
+      const unsigned long long w = cload(release_word(a));
+      s_k = (unsigned)(w >> 32);
+      cur = ctl_unpack((unsigned)w);
+      ok = aborted(a) ? 0 : 1;
+    }
+    if (wg_rank(a) == 0) load_tables(a, lead);
+    __syncthreads();
+    unsigned k = s_k;
+    for (;;) {
+      __syncthreads();
+      if (!ok || cur.phase == PH_DONE) break;
+      ++k;
+      run_phase<TB>(a, lds, lead, cur, nxt, ok, k);
+    }
+    __syncthreads();
+    if (!ok) break;   // a bounded wait gave up: this team stops
+  }
+}
+
+// Outcome of every problem of a batched call (one thread per problem, after
+// the batched kernel has finished).  A problem whose team stopped before
+// finishing it reports KP_STATUS_ABORTED.
+__global__ __launch_bounds__(64) void k_batch_info(BatchDesc d, kp_info* out) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= d.nprob) return;
+  const Args& a = batch_args(d.args, i);
+  const State* st = a.st;
+  const Pub* pb = a.pub;
+  kp_info r;
+  r.status = (a.sync[kSyncAbort] != 0u || pb->phase != PH_DONE) ? (int)KP_STATUS_ABORTED
+                                                                  : pb->status;
+  r.substeps = st->substeps;
+  r.rejected = st->rejected;
+  r.arnoldi_steps = st->arnoldi_steps;
+  r.expm_evals = st->expm_evals;
+  r.m_last = st->m_last;
+  r.n_fallback = st->n_fallback;
+  r.breakdowns = st->breakdowns;
+  r.schedule_len = min(st->nlog, kLogMax);
+  r.reserved = 0;
+  r.err_max = st->err_max;
+  r.mu = st->mu;
+  r.t_end = st->t;
+  out[i] = r;
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -207,6 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double ta
 using kp::Args;
 using kp::Pub;
 using kp::State;
+
+struct BatchCache;
 
 struct kp_ctx {
   kp_config cfg;
@@ -233,6 +337,7 @@ struct kp_ctx {
   Args last{};
   int have_begin = 0;
   int arn_target = 0;
+  BatchCache* batch = nullptr;   // plan, workspace and graph of the last batched call
   char err[512] = {0};
 };
 
@@ -312,6 +417,7 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.pb = p;
   r.tangent = 0;
   r.dout = nullptr;
+  r.wg0 = 0;
   r.npt = (int)npt;
   r.nx = A->nx;
   r.ny = A->ny;
@@ -402,6 +508,7 @@ void geometry(int ncu_slots, Args* a) {
   if ((a->nx & 1) && (rows & 1) && rows < a->ny) ++rows;
   a->rows_per_wg = (int)rows;
   a->nwg = (int)((a->ny + rows - 1) / rows);
+  a->nteam = a->nwg;
 }
 
 // Allocate the workspace for a problem and finish Args.
@@ -494,6 +601,240 @@ int fill_info(kp_ctx* ctx, kp_info* info) {
   return KP_OK;
 }
 
+// ---- batched call: plan, workspace, graph -------------------------------------
+
+// Planner inputs of one problem: its size and a Gershgorin-type bound of
+// ||A|| (the coefficient fields are not read: a pointwise term of unknown size
+// counts as 1 for ADR, 2 for the Allen-Cahn factor 1 - 3u^2, b + 1 + 2a^2 for
+// the Brusselator Jacobian).
+kp::PlanProblem plan_problem(const kp_op& A, int p, int m_max, double h) {
+  const double ix2 = 1.0 / (A.dx * A.dx), iy2 = 1.0 / (A.dy * A.dy);
+  const double nu = std::max(std::fabs(A.nu), A.kind == KP_OP_BRUSSELATOR ? std::fabs(A.nu2) : 0.0);
+  double rho = 4.0 * nu * (ix2 + iy2);
+  if (A.kind == KP_OP_ADR)
+    rho += std::fabs(A.ax) / A.dx + std::fabs(A.ay) / A.dy + std::fabs(A.react) + (A.field0 ? 1.0 : 0.0);
+  else if (A.kind == KP_OP_ALLEN_CAHN)
+    rho += 2.0;
+  else
+    rho += std::fabs(A.brus_b) + 1.0 + 2.0 * A.brus_a * A.brus_a;
+  kp::PlanProblem q;
+  q.nx = A.nx;
+  q.ny = A.ny;
+  q.n = (int64_t)A.nx * A.ny * (A.kind == KP_OP_BRUSSELATOR ? 2 : 1);
+  q.p = p;
+  q.c = (A.field0 ? 1 : 0) + (A.field1 ? 1 : 0);
+  q.m_max = m_max;
+  q.h_rho = std::fabs(h) * rho;
+  return q;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+struct BatchCache {
+  std::vector<long long> key;
+  kp::Plan plan;
+  int n_wg = 0;
+  int nprob = 0;
+  std::vector<int> team_of_prob;
+  std::vector<size_t> prob_off;       // arena offset of each problem's basis and state vector
+  std::vector<size_t> team_off;       // arena offset of each team's shared buffers
+  std::vector<int64_t> team_hx;       // halo doubles per workgroup of each team
+  std::vector<int64_t> flag_off;      // per problem, in unsigned
+  void* arena = nullptr;              // problem and team workspaces
+  State* st = nullptr;                // [nprob]
+  Pub* pub = nullptr;                 // [nprob]
+  unsigned* sync = nullptr;           // [nprob][16]
+  unsigned* flags = nullptr;
+  Args* d_args = nullptr;             // [nprob]
+  int* d_meta = nullptr;              // team_first | order | team_of_wg
+  kp_info* d_info = nullptr;          // [nprob]
+  std::vector<Args> hargs;
+  kp::BatchDesc desc{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(BatchCache* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  void* bufs[] = {b->arena, b->st, b->pub, b->sync, b->flags, b->d_args, b->d_meta, b->d_info};
+  for (void* x : bufs)
+    if (x) hipFree(x);
+  delete b;
+}
+
+template <typename TB>
+int batch_occupancy(kp_ctx* ctx, int* occ) {
+  KP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  occ, reinterpret_cast<const void*>(&kp::k_batch<TB>), kp::kThreads, 0));
+  return KP_OK;
+}
+
+// Team geometry of problem a on team t of the plan.
+void batch_geometry(const kp::Plan& pl, int t, Args* a) {
+  int rows, nw;
+  kp::plan_rows(a->nx, a->ny, pl.team_size[t], &rows, &nw);
+  a->rows_per_wg = rows;
+  a->nwg = nw;
+  a->nteam = pl.team_size[t];
+  a->wg0 = pl.team_wg0[t];
+}
+
+// New plan, allocations and graph for the problem set of `as` (validated).
+int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp::PlanProblem>& qs,
+                 std::vector<long long>&& key, BatchCache** out) {
+  BatchCache* b = new BatchCache();
+  b->key = std::move(key);
+  const int np = (int)as.size();
+  b->nprob = np;
+  const bool f32 = as[0].basis_f32 != 0;
+  int occ = 0;
+  int rc = f32 ? batch_occupancy<float>(ctx, &occ) : batch_occupancy<double>(ctx, &occ);
+  if (rc || occ < 1) {
+    batch_free(b);
+    if (!rc) snprintf(ctx->err, sizeof(ctx->err), "the batched kernel does not fit on a CU");
+    return rc ? rc : KP_EHIP;
+  }
+  b->n_wg = ctx->ncu * occ;
+  b->plan = kp::make_plan(qs, b->n_wg, kp::PlanModel());
+  const kp::Plan& pl = b->plan;
+  const int nt = (int)pl.team_size.size();
+  b->team_of_prob.assign(np, -1);
+  for (int t = 0; t < nt; ++t)
+    for (int q = pl.team_first[t]; q < pl.team_first[t + 1]; ++q) b->team_of_prob[pl.order[q]] = t;
+  // per problem: basis and state vector; per team: partial sums, halo rows,
+  // small-exponential scratch and tail values, sized for the team's problems
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  std::vector<int64_t> hxm(nt, 0);
+  for (int i = 0; i < np; ++i) {
+    const int t = b->team_of_prob[i];
+    hxm[t] = std::max<int64_t>(hxm[t], (int64_t)as[i].nplanes * 2 * as[i].nx);
+  }
+  size_t off = 0;
+  b->prob_off.assign(np, 0);
+  for (int i = 0; i < np; ++i) {
+    b->prob_off[i] = off;
+    off += align256((size_t)as[i].ld * (as[i].m_max + 2) * esz);       // V
+    off += align256((size_t)as[i].ld * sizeof(double));                // u
+  }
+  b->team_off.assign(nt, 0);
+  b->team_hx = hxm;
+  for (int t = 0; t < nt; ++t) {
+    b->team_off[t] = off;
+    if (hxm[t] == 0) continue;
+    const int g = pl.team_size[t];
+    off += align256((size_t)g * kp::kKStride * sizeof(double));          // part
+    off += align256((size_t)g * hxm[t] * sizeof(double));                // hx
+    off += align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);  // ex
+    off += align256(sizeof(double) * kp::kTailPad);                      // tx
+  }
+  b->flag_off.assign(np, 0);
+  int64_t nflags = 0;
+  std::vector<Args> hs = as;
+  for (int i = 0; i < np; ++i) {
+    batch_geometry(pl, b->team_of_prob[i], &hs[i]);
+    b->flag_off[i] = nflags;
+    nflags += (int64_t)hs[i].nwg * kp::kFlagStride;
+  }
+  hipError_t e = hipMalloc(&b->arena, std::max<size_t>(off, 256));
+  if (e == hipSuccess) e = hipMalloc(&b->st, sizeof(State) * np);
+  if (e == hipSuccess) e = hipMalloc(&b->pub, sizeof(Pub) * np);
+  if (e == hipSuccess) e = hipMalloc(&b->sync, 64 * (size_t)np);
+  if (e == hipSuccess) e = hipMalloc(&b->flags, sizeof(unsigned) * (size_t)std::max<int64_t>(nflags, 1));
+  if (e == hipSuccess) e = hipMalloc(&b->d_args, sizeof(Args) * np);
+  const size_t nmeta = (size_t)(nt + 1) + np + b->n_wg;
+  if (e == hipSuccess) e = hipMalloc(&b->d_meta, sizeof(int) * nmeta);
+  if (e == hipSuccess) e = hipMalloc(&b->d_info, sizeof(kp_info) * np);
+  if (e != hipSuccess) {
+    snprintf(ctx->err, sizeof(ctx->err), "batched workspace: %s", hipGetErrorString(e));
+    batch_free(b);
+    return KP_ENOMEM;
+  }
+  std::vector<int> meta;
+  meta.reserve(nmeta);
+  meta.insert(meta.end(), pl.team_first.begin(), pl.team_first.end());
+  meta.insert(meta.end(), pl.order.begin(), pl.order.end());
+  meta.insert(meta.end(), pl.team_of_wg.begin(), pl.team_of_wg.end());
+  e = hipMemcpy(b->d_meta, meta.data(), sizeof(int) * nmeta, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(ctx, e, "hipMemcpy(plan)");
+  }
+  b->desc.args = (const kp::CArgs*)(b->d_args);
+  b->desc.team_first = b->d_meta;
+  b->desc.order = b->d_meta + (nt + 1);
+  b->desc.team_of_wg = b->d_meta + (nt + 1) + np;
+  b->desc.nprob = np;
+  // the graph: reset of every problem -> the persistent batched kernel
+  // (cooperative) -> the per-problem outcome records
+  hipGraphNode_t n1, n2, n3;
+  void* a1[] = {&b->desc};
+  void* a2[] = {&b->desc};
+  void* a3[] = {&b->desc, &b->d_info};
+  hipKernelNodeParams p1{}, p2{}, p3{};
+  p1.func = reinterpret_cast<void*>(&kp::k_batch_init);
+  p1.gridDim = dim3(np);
+  p1.blockDim = dim3(256);
+  p1.kernelParams = a1;
+  p2.func = f32 ? reinterpret_cast<void*>(&kp::k_batch<float>) : reinterpret_cast<void*>(&kp::k_batch<double>);
+  p2.gridDim = dim3(b->n_wg);
+  p2.blockDim = dim3(kp::kThreads);
+  p2.kernelParams = a2;
+  p3.func = reinterpret_cast<void*>(&kp::k_batch_info);
+  p3.gridDim = dim3((np + 63) / 64);
+  p3.blockDim = dim3(64);
+  p3.kernelParams = a3;
+  hipLaunchAttributeValue coop{};
+  coop.cooperative = 1;
+  e = hipGraphCreate(&b->graph, 0);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n1, b->graph, nullptr, 0, &p1);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n2, b->graph, &n1, 1, &p2);
+  if (e == hipSuccess) e = hipGraphKernelNodeSetAttribute(n2, hipKernelNodeAttributeCooperative, &coop);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&n3, b->graph, &n2, 1, &p3);
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(ctx, e, "batched graph");
+  }
+  *out = b;
+  return KP_OK;
+}
+
+// Per-call Args of every problem: the caller's pointers and coefficients,
+// the team geometry and the team / problem buffers.
+void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ticks) {
+  const kp::Plan& pl = b->plan;
+  b->hargs = as;
+  for (int i = 0; i < b->nprob; ++i) {
+    Args& a = b->hargs[i];
+    const int t = b->team_of_prob[i];
+    batch_geometry(pl, t, &a);
+    const size_t esz = a.basis_f32 ? sizeof(float) : sizeof(double);
+    char* pbase = static_cast<char*>(b->arena) + b->prob_off[i];
+    a.V = pbase;
+    a.u = reinterpret_cast<double*>(pbase + align256((size_t)a.ld * (a.m_max + 2) * esz));
+    char* base = static_cast<char*>(b->arena) + b->team_off[t];
+    const int g = pl.team_size[t];
+    a.part = reinterpret_cast<double*>(base);
+    base += align256((size_t)g * kp::kKStride * sizeof(double));
+    a.hx = reinterpret_cast<double*>(base);
+    base += align256((size_t)g * b->team_hx[t] * sizeof(double));
+    a.ex = reinterpret_cast<double*>(base);
+    base += align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);
+    a.tx = reinterpret_cast<double*>(base);
+    a.st = b->st + i;
+    a.pub = b->pub + i;
+    a.sync = b->sync + 16 * (size_t)i;
+    a.flags = b->flags + b->flag_off[i];
+    a.wait_ticks = wait_ticks;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -541,6 +882,7 @@ int kp_set_config(kp_ctx* ctx, const kp_config* cfg) {
 int kp_destroy(kp_ctx* ctx) {
   if (!ctx) return KP_EINVAL;
   if (ctx->ncu > 0) hipStreamSynchronize(ctx->stream);
+  batch_free(ctx->batch);
   void* bufs[] = {ctx->V,  ctx->u,    ctx->part, ctx->hx, ctx->flags,
                   ctx->st, ctx->pub, ctx->sync, ctx->ex, ctx->tx};
   for (void* b : bufs)
@@ -694,6 +1036,84 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
         V_host[(size_t)c * L + a.N + k] = at(a.tail_off + k) * scale;
     }
   }
+  return KP_OK;
+}
+
+int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops, const double* const* B,
+                         const int32_t* p, const int64_t* ldb, const double* h, double tol,
+                         int32_t m_max, double* const* out, kp_info* infos) {
+  if (!ctx || nprob < 1 || !ops || !B || !p || !ldb || !h || !out) return KP_EINVAL;
+  int rc = device_setup(ctx);
+  if (rc) return rc;
+  std::vector<Args> as(nprob);
+  std::vector<kp::PlanProblem> qs(nprob);
+  std::vector<std::pair<uintptr_t, uintptr_t>> spans(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    if ((rc = build_args(ctx, &ops[i], B[i], p[i], ldb[i], h[i], tol, m_max, out[i], true, &as[i])))
+      return rc;
+    qs[i] = plan_problem(ops[i], p[i], m_max, h[i]);
+    const uintptr_t o = reinterpret_cast<uintptr_t>(out[i]);
+    spans[i] = {o, o + (uintptr_t)as[i].N * sizeof(double)};
+  }
+  // outputs of different problems must not overlap (each team writes its own)
+  std::sort(spans.begin(), spans.end());
+  for (int i = 1; i < nprob; ++i)
+    if (spans[i].first < spans[i - 1].second) return KP_EINVAL;
+  std::vector<long long> key = {nprob, m_max, ctx->cfg.basis_dtype, ctx->cfg.orth,
+                                ctx->cfg.fixed_m, ctx->cfg.fixed_substeps};
+  for (int i = 0; i < nprob; ++i) {
+    key.push_back(ops[i].kind);
+    key.push_back(ops[i].nx);
+    key.push_back(ops[i].ny);
+    key.push_back(p[i]);
+  }
+  if (!ctx->batch || ctx->batch->key != key) {
+    if (ctx->batch) {
+      KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      batch_free(ctx->batch);
+      ctx->batch = nullptr;
+    }
+    if ((rc = batch_create(ctx, as, qs, std::move(key), &ctx->batch))) return rc;
+  }
+  BatchCache* b = ctx->batch;
+  batch_fill_args(b, as, ctx->wait_ticks);
+  KP_HIP(ctx, hipMemcpyAsync(b->d_args, b->hargs.data(), sizeof(Args) * nprob,
+                             hipMemcpyHostToDevice, ctx->stream));
+  KP_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  ctx->have_begin = 0;
+  if (infos) {
+    KP_HIP(ctx, hipMemcpyAsync(infos, b->d_info, sizeof(kp_info) * nprob, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return KP_OK;
+}
+
+int kp_batch_plan(int32_t nprob, const kp_op* ops, const int32_t* p, const double* h,
+                  int32_t m_max, int32_t n_wg, int32_t* team_of_problem, int32_t* team_wg0,
+                  int32_t* team_size, int32_t* nteams, double* makespan, double* work) {
+  if (nprob < 1 || !ops || !p || !h || n_wg < 1 || !team_of_problem || !team_wg0 ||
+      !team_size || !nteams)
+    return KP_EINVAL;
+  if (m_max < 1 || m_max > KP_MMAX) return KP_EINVAL;
+  std::vector<kp::PlanProblem> qs(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const kp_op& A = ops[i];
+    if (A.nx < 1 || A.ny < 1 || !(A.dx > 0.0) || !(A.dy > 0.0) || p[i] < 0 || p[i] > KP_PMAX ||
+        !std::isfinite(h[i]) || A.kind < KP_OP_ADR || A.kind > KP_OP_BRUSSELATOR)
+      return KP_EINVAL;
+    qs[i] = plan_problem(A, p[i], m_max, h[i]);
+  }
+  const kp::Plan pl = kp::make_plan(qs, n_wg, kp::PlanModel());
+  const int nt = (int)pl.team_size.size();
+  for (int t = 0; t < nt; ++t) {
+    team_wg0[t] = pl.team_wg0[t];
+    team_size[t] = pl.team_size[t];
+    for (int q = pl.team_first[t]; q < pl.team_first[t + 1]; ++q) team_of_problem[pl.order[q]] = t;
+  }
+  *nteams = nt;
+  if (makespan) *makespan = pl.makespan;
+  if (work) *work = pl.work;
   return KP_OK;
 }
 

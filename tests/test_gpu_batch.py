@@ -1,0 +1,177 @@
+"""Parity of the batched entry point (kp_phi_combo_batched) with the oracle,
+with the DFT closed form and with the single-problem entry point."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import closed_form, krylov
+import paper_2410_14917_amd as kp
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def dev(pr):
+    op = kp.Operator.from_host(pr.op, device="cuda")
+    B = torch.as_tensor(np.ascontiguousarray(pr.B[:, :pr.p + 1].T), device="cuda")
+    return op, B
+
+
+# mixed kinds, sizes (odd nx, single row, 2-species), p and h
+MIXED = [
+    (W.OP_ADR, 64, 48, 3, 0.05),
+    (W.OP_ADR, 45, 33, 0, 0.1),
+    (W.OP_ADR, 17, 1, 2, 0.05),
+    (W.OP_ALLEN_CAHN, 80, 72, 2, 0.1),
+    (W.OP_BRUSSELATOR, 50, 41, 2, 0.01),
+    (W.OP_ADR, 128, 100, 4, 0.02),
+    (W.OP_ADR, 31, 29, 1, 0.2),
+    (W.OP_ALLEN_CAHN, 40, 40, 3, 0.05),
+    (W.OP_ADR, 96, 7, 2, 0.05),
+    (W.OP_BRUSSELATOR, 24, 24, 1, 0.02),
+]
+
+
+def _mixed(seed):
+    return [W.random_problem(seed + i, kind=k, nx=nx, ny=ny, p=p, h=h, with_diag=(i % 2 == 0),
+                             nu=0.01 if k != W.OP_BRUSSELATOR else 0.02)
+            for i, (k, nx, ny, p, h) in enumerate(MIXED)]
+
+
+@pytest.mark.parametrize("orth", [("h-gsmgs", "gsmgs"), ("h-cwy", "cwy")])
+def test_batched_fixed_schedule_matches_oracle(orth):
+    probs = _mixed(100)
+    devs = [dev(pr) for pr in probs]
+    m, nsub = 24, 2
+    say(f"batched fixed m={m} nsub={nsub} {orth[0]}: {len(probs)} problems")
+    with kp.Context(orth=orth[0], fixed_m=m, fixed_substeps=nsub) as ctx:
+        ys, infos = ctx.phi_combo_batched([d[0] for d in devs], [d[1] for d in devs],
+                                          [pr.h for pr in probs], m_max=m, info=True)
+    for i, (pr, y, inf) in enumerate(zip(probs, ys, infos)):
+        ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=m, fixed_substeps=nsub,
+                                      m_max=m, orth="hybrid", tform=orth[1])
+        e = rel(y.cpu().numpy(), ref)
+        say(f"  [{i}] kind={pr.op.kind} {pr.op.nx}x{pr.op.ny} p={pr.p} rel={e:.2e} {inf['status']}")
+        assert inf["status"] == 0 and inf["substeps"] == nsub
+        assert inf["arnoldi_steps"] == rinfo.arnoldi_steps
+        assert e <= FP64_TOL
+
+
+def test_batched_adaptive_matches_oracle_and_single_calls():
+    probs = _mixed(200)
+    devs = [dev(pr) for pr in probs]
+    tol, m_max = 1e-8, 32
+    with kp.Context() as ctx:
+        ys, infos = ctx.phi_combo_batched([d[0] for d in devs], [d[1] for d in devs],
+                                          [pr.h for pr in probs], tol=tol, m_max=m_max,
+                                          info=True)
+        singles = [ctx.phi_combo(d[0], d[1], pr.h, tol=tol, m_max=m_max, info=True)
+                   for d, pr in zip(devs, probs)]
+    for i, (pr, y, inf, (y1, inf1)) in enumerate(zip(probs, ys, infos, singles)):
+        ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, tol=tol, m_max=m_max,
+                                      orth="hybrid", tform="gsmgs")
+        y = y.cpu().numpy()
+        say(f"  [{i}] kind={pr.op.kind} {pr.op.nx}x{pr.op.ny} substeps {inf['substeps']} "
+            f"(oracle {rinfo.substeps}) rel oracle {rel(y, ref):.2e} "
+            f"single {rel(y, y1.cpu().numpy()):.2e}")
+        assert inf["status"] == 0 and inf["t_end"] == pr.h
+        assert inf["substeps"] == rinfo.substeps and inf["rejected"] == rinfo.rejected
+        assert inf["substeps"] == inf1["substeps"] and inf["arnoldi_steps"] == inf1["arnoldi_steps"]
+        assert rel(y, ref) <= FP64_TOL
+        assert rel(y, y1.cpu().numpy()) <= 1e-12
+
+
+def test_many_small_problems_against_closed_form():
+    """300 advection-diffusion-reaction problems (sides 16..48): teams of one
+    workgroup that solve several problems one after another."""
+    rng = np.random.default_rng(301)
+    hs, ops_h, Bs_h = [], [], []
+    for i in range(300):
+        nx, ny = int(rng.integers(16, 49)), int(rng.integers(16, 49))
+        nu = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e-1))))
+        op = W.Operator(kind=W.OP_ADR, nx=nx, ny=ny, nu=nu, ax=1.0, ay=0.5,
+                        react=float(rng.uniform(-1, 1)))
+        ops_h.append(op)
+        Bs_h.append(rng.standard_normal((op.n, 4)))
+        hs.append(0.05)
+    ops = [kp.Operator.from_host(o) for o in ops_h]
+    Bs = [torch.as_tensor(np.ascontiguousarray(B.T), device="cuda") for B in Bs_h]
+    tol = 1e-8
+    with kp.Context() as ctx:
+        ys, infos = ctx.phi_combo_batched(ops, Bs, hs, tol=tol, m_max=48, info=True)
+    worst = 0.0
+    for o, B, h, y, inf in zip(ops_h, Bs_h, hs, ys, infos):
+        assert inf["status"] == 0 and inf["t_end"] == h
+        worst = max(worst, rel(y.cpu().numpy(), closed_form.adr_phi_combo(o, B, h, 3)))
+    say(f"  300 problems: worst rel err vs closed form {worst:.2e}")
+    assert worst <= 10 * tol
+
+
+def test_graph_replays_and_new_inputs():
+    """The graph of a problem set is replayed while the shapes repeat; eager
+    work in between; a replay with new B values matches the single calls."""
+    probs = _mixed(400)
+    devs = [dev(pr) for pr in probs]
+    ops, Bs, hs = [d[0] for d in devs], [d[1] for d in devs], [pr.h for pr in probs]
+    with kp.Context() as ctx:
+        first = [y.clone() for y in ctx.phi_combo_batched(ops, Bs, hs, tol=1e-8, m_max=32)]
+        for rep in range(3):
+            junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+            (junk * 2.0).sum().item()                         # eager work between replays
+            ctx.phi_combo(ops[0], Bs[0], hs[0], tol=1e-8, m_max=32)
+            again = ctx.phi_combo_batched(ops, Bs, hs, tol=1e-8, m_max=32)
+            torch.cuda.synchronize()
+            for y0, y1 in zip(first, again):
+                assert torch.equal(y0, y1), f"replay {rep} differs"
+        Bs2 = [3.0 * B + 1.0 for B in Bs]
+        new = ctx.phi_combo_batched(ops, Bs2, hs, tol=1e-8, m_max=32)
+        for i in range(len(ops)):
+            y1 = ctx.phi_combo(ops[i], Bs2[i], hs[i], tol=1e-8, m_max=32)
+            assert rel(new[i].cpu().numpy(), y1.cpu().numpy()) <= 1e-12
+
+
+def test_batched_rejects_overlapping_outputs():
+    probs = _mixed(500)[:3]
+    devs = [dev(pr) for pr in probs]
+    n = max(pr.op.n for pr in probs)
+    buf = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    outs = [buf[:probs[0].op.n], buf[1:1 + probs[1].op.n], buf[n:n + probs[2].op.n]]
+    with kp.Context() as ctx:
+        with pytest.raises(RuntimeError, match=r"\[-1\]"):
+            ctx.phi_combo_batched([d[0] for d in devs], [d[1] for d in devs],
+                                  [pr.h for pr in probs], outs=outs)
+
+
+def test_full_size_uneven_batch_against_closed_form():
+    """512 advection-diffusion-reaction problems, sides U{32..512}
+    (N 1,024 .. 262,144, sum ~5.0e7), p = 3, h = 0.05, m <= 48, tol 1e-8, in
+    one batched call; every problem against the DFT closed form."""
+    probs = W.config4()
+    say(f"full-size batch: {len(probs)} problems, N total {sum(q.op.n for q in probs)}")
+    ops = [kp.Operator.from_host(q.op) for q in probs]
+    Bs = [torch.as_tensor(np.ascontiguousarray(q.B.T), device="cuda") for q in probs]
+    with kp.Context() as ctx:
+        ys, infos = ctx.phi_combo_batched(ops, Bs, [q.h for q in probs], tol=1e-8, m_max=48,
+                                          info=True)
+    say("full-size batch: closed forms")
+    worst, steps = 0.0, 0
+    for q, y, inf in zip(probs, ys, infos):
+        assert inf["status"] == 0 and inf["t_end"] == q.h
+        steps += inf["arnoldi_steps"]
+        worst = max(worst, rel(y.cpu().numpy(), closed_form.adr_phi_combo(q.op, q.B, q.h, q.p)))
+    say(f"  arnoldi steps {steps}, worst rel err vs closed form {worst:.2e}")
+    assert worst <= 10 * 1e-8
