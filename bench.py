@@ -102,6 +102,8 @@ def main():
                     help="skip the FP32-basis leg (2 x 2048^2 Brusselator)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (advection-diffusion 1024^2, least-squares loss)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched leg (512 uneven advection-diffusion-reaction problems)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -329,6 +331,67 @@ def main():
         }
         print(f"[bench] adjoint leg: {result['adjoint']}", file=sys.stderr, flush=True)
         del B5, y5
+
+    # ---- batched uneven problems: one launch vs one call per problem --------
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        probs4 = W.config4()
+        ops4 = [kp.Operator.from_host(q.op, device=dev) for q in probs4]
+        Bs4 = [torch.as_tensor(np.ascontiguousarray(q.B.T), device=dev) for q in probs4]
+        hs4 = [q.h for q in probs4]
+        outs4 = [torch.empty(q.op.n, dtype=torch.float64, device=dev) for q in probs4]
+        tol4, mm4 = probs4[0].tol, probs4[0].m_max
+        c4 = kp.Context(orth=args.orth, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf4 = c4.phi_combo_batched(ops4, Bs4, hs4, tol=tol4, m_max=mm4, outs=outs4, info=True)
+        first_s = time.perf_counter() - t0
+        nrep = 3
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(nrep)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nrep):
+            e0[k].record(stream)
+            c4.phi_combo_batched(ops4, Bs4, hs4, tol=tol4, m_max=mm4, outs=outs4)
+            e1[k].record(stream)
+        torch.cuda.synchronize()
+        batch_wall = (time.perf_counter() - t0) / nrep
+        batch_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(e0, e1)]))
+        steps4 = sum(r["arnoldi_steps"] for r in inf4)
+        bytes4 = sum(vectors_per_call(c4.batch_schedule(i), q.p, 0) * 8.0 * q.op.n
+                     for i, q in enumerate(probs4))
+        _, _, plan_s, work_s = kp.batch_plan([q.op for q in probs4], [q.p for q in probs4], hs4,
+                                             m_max=mm4, n_wg=256)
+        # one plain call per problem (the largest first, so the workspace is
+        # allocated before the timed loop)
+        big = max(range(len(probs4)), key=lambda i: probs4[i].op.n)
+        c4.phi_combo(ops4[big], Bs4[big], hs4[big], tol=tol4, m_max=mm4, out=outs4[big])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(len(probs4)):
+            c4.phi_combo(ops4[i], Bs4[i], hs4[i], tol=tol4, m_max=mm4, out=outs4[i])
+        torch.cuda.synchronize()
+        seq_s = time.perf_counter() - t0
+        c4.close()
+        result["batched"] = {
+            "workload": f"{len(probs4)} advection-diffusion-reaction problems, sides U{{32..512}}, "
+                        f"N total {sum(q.op.n for q in probs4)}, nu logU[1e-3,1e-1], r U[-1,1], "
+                        f"h={hs4[0]}, p={probs4[0].p}, tol={tol4}, m<={mm4}",
+            "batched_ms": round(batch_ms, 2), "batched_wall_ms": round(1e3 * batch_wall, 2),
+            "first_call_s": round(first_s, 3),
+            "sequential_ms": round(1e3 * seq_s, 1),
+            "speedup_vs_sequential": round(1e3 * seq_s / batch_ms, 2),
+            "arnoldi_steps": steps4,
+            "arnoldi_steps_per_s": round(steps4 / (batch_ms * 1e-3), 1),
+            "modelled_GBps": round(bytes4 / (batch_ms * 1e-3) / 1e9, 1),
+            "frac": round(bytes4 / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "plan_makespan_ms": round(1e3 * plan_s, 1),
+            "plan_balanced_ms": round(1e3 * work_s / 256, 1),
+            "status_ok": all(r["status"] == 0 for r in inf4),
+        }
+        print(f"[bench] batched leg: {result['batched']}", file=sys.stderr, flush=True)
+        del Bs4, outs4
 
     # ---- CPU oracle baseline (bounded sample) --------------------------------
     if not args.no_cpu:

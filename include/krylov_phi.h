@@ -219,6 +219,12 @@ int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops,
                          const double* h, double tol, int32_t m_max,
                          double* const* out, kp_info* infos);
 
+/* Copy the (tau, m) of the accepted substeps of problem i of the last batched
+ * call into host arrays of capacity cap; returns the number copied (>= 0) or
+ * a KP_E code (KP_ESTATE: no batched call yet; KP_EINVAL: i out of range). */
+int kp_get_batch_schedule(kp_ctx* ctx, int32_t i, double* tau_host, int32_t* m_host,
+                          int32_t cap);
+
 /*
  * The planner of kp_phi_combo_batched on its own (host only; no device call,
  * the operators' field pointers are only tested for NULL).  For a grid of

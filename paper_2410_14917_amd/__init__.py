@@ -187,6 +187,17 @@ class Context:
                                                 m.ctypes.data_as(ctypes.c_void_p), cap), self.h)
         return list(zip(tau[:n].tolist(), m[:n].tolist()))
 
+    def batch_schedule(self, i: int, cap: int = 8192):
+        """(tau, m) of the accepted substeps of problem i of the last batched call."""
+        import numpy as np
+        tau = np.zeros(cap)
+        m = np.zeros(cap, dtype=np.int32)
+        n = _lib.check(self.lib.kp_get_batch_schedule(self.h, int(i),
+                                                      tau.ctypes.data_as(ctypes.c_void_p),
+                                                      m.ctypes.data_as(ctypes.c_void_p), cap),
+                       self.h)
+        return list(zip(tau[:n].tolist(), m[:n].tolist()))
+
     def arnoldi_begin(self, op: Operator, B, m_max: int):
         p, ldb = self._check_B(B, op.n)
         self._arn = (op, B, m_max, p)

@@ -25,7 +25,7 @@ BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
 
 # Exported symbols (every function declared in the header).
 SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_tangent",
-           "kp_phi_combo_batched", "kp_batch_plan", "kp_get_schedule",
+           "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
            "kp_strerror", "kp_last_error", "kp_version")
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(KpInfo)]
     lib.kp_batch_plan.argtypes = [I32, ctypes.POINTER(KpOp), PI32, PD, I32, I32, PI32, PI32, PI32,
                                   PI32, PD, PD]
+    lib.kp_get_batch_schedule.argtypes = [P, I32, P, P, I32]
     lib.kp_get_schedule.argtypes = [P, P, P, I32]
     lib.kp_arnoldi_begin.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, I32]
     lib.kp_arnoldi_step.argtypes = [P, I32]

@@ -1089,6 +1089,23 @@ int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops, const dou
   return KP_OK;
 }
 
+int kp_get_batch_schedule(kp_ctx* ctx, int32_t i, double* tau_host, int32_t* m_host,
+                          int32_t cap) {
+  if (!ctx || cap < 0 || (cap > 0 && (!tau_host || !m_host))) return KP_EINVAL;
+  if (!ctx->batch) return KP_ESTATE;
+  if (i < 0 || i >= ctx->batch->nprob) return KP_EINVAL;
+  KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const State* st = ctx->batch->st + i;
+  int nlog = 0;
+  KP_HIP(ctx, hipMemcpy(&nlog, &st->nlog, sizeof(int), hipMemcpyDeviceToHost));
+  const int n = std::min(std::min(nlog, kp::kLogMax), cap);
+  if (n > 0) {
+    KP_HIP(ctx, hipMemcpy(tau_host, st->log_tau, n * sizeof(double), hipMemcpyDeviceToHost));
+    KP_HIP(ctx, hipMemcpy(m_host, st->log_m, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  return n;
+}
+
 int kp_batch_plan(int32_t nprob, const kp_op* ops, const int32_t* p, const double* h,
                   int32_t m_max, int32_t n_wg, int32_t* team_of_problem, int32_t* team_wg0,
                   int32_t* team_size, int32_t* nteams, double* makespan, double* work) {

@@ -79,9 +79,10 @@ def test_batched_adaptive_matches_oracle_and_single_calls():
         ys, infos = ctx.phi_combo_batched([d[0] for d in devs], [d[1] for d in devs],
                                           [pr.h for pr in probs], tol=tol, m_max=m_max,
                                           info=True)
+        scheds = [ctx.batch_schedule(i) for i in range(len(probs))]
         singles = [ctx.phi_combo(d[0], d[1], pr.h, tol=tol, m_max=m_max, info=True)
                    for d, pr in zip(devs, probs)]
-    for i, (pr, y, inf, (y1, inf1)) in enumerate(zip(probs, ys, infos, singles)):
+    for i, (pr, y, inf, (y1, inf1), sch) in enumerate(zip(probs, ys, infos, singles, scheds)):
         ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, tol=tol, m_max=m_max,
                                       orth="hybrid", tform="gsmgs")
         y = y.cpu().numpy()
@@ -90,6 +91,9 @@ def test_batched_adaptive_matches_oracle_and_single_calls():
             f"single {rel(y, y1.cpu().numpy()):.2e}")
         assert inf["status"] == 0 and inf["t_end"] == pr.h
         assert inf["substeps"] == rinfo.substeps and inf["rejected"] == rinfo.rejected
+        assert [m for _, m in sch] == [m for _, m in rinfo.schedule]
+        assert np.allclose([t for t, _ in sch], [t for t, _ in rinfo.schedule], rtol=0,
+                           atol=1e-6 * pr.h)
         assert inf["substeps"] == inf1["substeps"] and inf["arnoldi_steps"] == inf1["arnoldi_steps"]
         assert rel(y, ref) <= FP64_TOL
         assert rel(y, y1.cpu().numpy()) <= 1e-12
