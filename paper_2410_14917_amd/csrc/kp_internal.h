@@ -126,7 +126,7 @@ struct Args {
   int pb;             // number of phi terms beyond b_0 (columns b_1..b_pb of B)
   int tangent;        // 1: Van Loan block operator [[Atilde, dAtilde], [0, Atilde]]
   int nwg, rows_per_wg;   // workgroups that own rows; rows per workgroup
-  int nteam, wg0;     // workgroups meeting at the barriers (>= nwg), first one's blockIdx
+  int nteam, wg0;     // workgroups meeting at the barriers (>= nwg); first workgroup of the run of such teams
   int kind, transpose;
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
   double dcx, dcy, dadx, dady, dreact;   // tangent mode: the direction dA
@@ -139,9 +139,13 @@ struct Args {
   int64_t wait_ticks; // bound of a grid-wide wait, steady-counter ticks
 };
 
-// Rank of this workgroup in the set that solves the problem (the whole grid
-// for a single call, a team of the grid for a batched call).  Rank 0 leads.
-__device__ inline int wg_rank(const Args& a) { return (int)blockIdx.x - a.wg0; }
+// Rank of this workgroup in the set that solves the problem: the whole grid
+// for a single call (wg0 = 0, nteam = grid size); for a batched call, the
+// teams of one size are consecutive runs of nteam workgroups from wg0.
+// Rank 0 leads.
+__device__ inline int wg_rank(const Args& a) {
+  return (int)(((unsigned)blockIdx.x - (unsigned)a.wg0) % (unsigned)a.nteam);
+}
 
 // ---- coherent (agent-scope) accesses ---------------------------------------
 

@@ -4,14 +4,18 @@
 // workgroups.  A team solves its problems one after another, each with the
 // single-problem machinery (row ownership inside the team, one team-wide
 // barrier per phase, the team's first workgroup as leader).  The plan fixes
-// the team sizes and the ordered problem list of every team before the
-// launch.
+// the team sizes and which class of teams (teams of one size) each problem
+// goes to; on the device the teams of a class take their class's problems,
+// heaviest first, as they become free.
 //
 // Cost model of one problem on a team of g workgroups (seconds):
-//   steps    S  = max(16, 8 sqrt(h rho)), rho = a Gershgorin bound of ||A||
-//               (fit of the substep controller's operator applications for
-//               tol ~1e-8 over h rho in [4, 2e4]; the controller takes
-//               O(sqrt(h rho)) steps on these diffusion-dominated spectra)
+//   steps    S  = max(16, 8 sqrt(h rho)) for h rho < 64 (one substep, m
+//               grown by doubling), 9.5 sqrt(h rho) above (substeps of
+//               m_max = 48), rho = a Gershgorin bound of ||A||: least-squares
+//               fits of the measured step counts of 512 advection-diffusion-
+//               reaction problems at tol 1e-8 (h rho from 0.4 to 1e4); the
+//               controller takes O(sqrt(h rho)) steps on these
+//               diffusion-dominated spectra
 //   m_eff       = min(S, m_max) (Krylov dimension of a substep)
 //   passes   P  = S (m_eff + p + c + 6) vectors of N float64 (the per-step
 //               traffic 2j + p + c + 5 averaged over a substep, plus combine)
@@ -67,7 +71,8 @@ struct Plan {
 };
 
 inline double plan_steps(const PlanProblem& q) {
-  return std::max(16.0, 8.0 * std::sqrt(std::max(0.0, q.h_rho)));
+  const double r = std::sqrt(std::max(0.0, q.h_rho));
+  return q.h_rho < 64.0 ? std::max(16.0, 8.0 * r) : 9.5 * r;
 }
 
 // Row geometry of a problem on a team of g workgroups: rows per workgroup

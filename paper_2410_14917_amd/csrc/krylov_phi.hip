@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
 // Reset of the call state; the Hessenberg and correction matrices are zeroed
 // so that entries outside their triangles read as zero.  Run by one
 // workgroup of any size before the launch that solves the problem.
-__device__ inline void init_problem(const Args& a, int m_target) {
+__device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   State* st = a.st;
   for (int i = kp_tid(); i < kLdh * kMMax; i += blockDim.x) st->H[i] = 0.0;
   for (int i = kp_tid(); i < kLdt * kMMax; i += blockDim.x) {
@@ -170,7 +170,7 @@ __device__ inline void init_problem(const Args& a, int m_target) {
     st->Minv[i] = 0.0;
   }
   for (int i = kp_tid(); i < kMMax + 2; i += blockDim.x) a.pub->coef[i] = 0.0;
-  for (int i = kp_tid(); i < a.nwg * kFlagStride; i += blockDim.x) a.flags[i] = 0u;
+  for (int i = kp_tid(); i < nflags; i += blockDim.x) a.flags[i] = 0u;
   if (kp_tid() != 0) return;
   for (int i = 0; i < 16; ++i) a.sync[i] = 0u;   // counters, release word (STAGE), abort
   Pub* pb = a.pub;
@@ -195,44 +195,81 @@ __device__ inline void init_problem(const Args& a, int m_target) {
   st->err_max = st->omega = st->err = st->last_nrm2 = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_init(Args a, int m_target) { init_problem(a, m_target); }
+__global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
+  init_problem(a, m_target, a.nwg * kFlagStride);
+}
 
 // ---- batched call ------------------------------------------------------------
 //
 // Many independent problems in one cooperative launch.  The grid is split into
-// teams of consecutive workgroups (team_of_wg); team t solves the problems
-// order[team_first[t] .. team_first[t+1]) one after another, each exactly as a
-// single call would (its own Args, State, control block and barrier words),
-// so the phases, barriers and coherence rules are those of k_run inside each
-// team.  Every problem also has its own basis and state vector: reusing them
-// for the team's next problem would hand cache lines written with plain
-// stores to other workgroups (other rows, other XCDs) within the launch, and
-// the L2s of different XCDs are not coherent for plain stores.  Only the
-// team's small buffers that are accessed with coherent atomics (partial sums,
-// halo rows, tail values) and the leader's small-exponential scratch (always
-// the same workgroup) are shared by a team's problems; a problem's last
-// barrier (FINISH -> DONE) is passed by every workgroup of the team before
-// any of them touches those for the next problem.
+// teams of consecutive workgroups; the teams of one size form a class and
+// occupy a consecutive run of the grid.  Each class has a queue of problems,
+// heaviest first (the host planner's assignment).  A team's leader takes the
+// next problem from the front of its class's queue and, once that is empty,
+// the lightest remaining problem from the back of the queue of a class of
+// smaller teams, and hands it to the team's other workgroups through the
+// team's slot.  The team
+// then solves it exactly as a single call would (its own Args with the
+// class's geometry, State, control block and barrier words), so the phases,
+// barriers and coherence rules are those of k_run inside each team.  Every
+// buffer a problem writes is its own (basis, state vector, partial sums, halo
+// rows, tail values, small-exponential scratch): a team never takes over
+// memory another workgroup wrote with plain stores in the same launch (the
+// L2s of different XCDs are not coherent for plain stores).  A problem's last
+// barrier (FINISH -> DONE) is passed by the whole team before its leader
+// takes the next one.
+//
 // The Args records are read through the constant address space: they are not
 // written during the launch and every access has a uniform address, so their
 // fields are fetched with scalar loads, as kernel arguments are.
 typedef __attribute__((address_space(4))) const Args CArgs;
 
 struct BatchDesc {
-  const CArgs* args;       // [nprob], not written during the launch
-  const int* team_first;   // [nteams + 1]
-  const int* order;        // [nprob] problem indices grouped by team
-  const int* team_of_wg;   // [grid] (-1: no work)
-  int nprob;
+  const CArgs* args;       // [nclass][nprob], not written during the launch
+  const int* order;        // problems of class c, heaviest first: order[class_first[c] ..)
+  const int* class_first;  // [nclass + 1]
+  const int* team_of_wg;   // [grid] (-1: no team)
+  const int* team_class;   // [nteams]
+  const int* team_wg0;     // [nteams]
+  unsigned long long* queue;   // [nclass]: front (low 32 bits), back (high) (coherent)
+  unsigned long long* slot;    // [nteams * 8]: (sequence << 32) | (problem + 1) (coherent)
+  int nprob, nclass, nteams;
+  int64_t wait_ticks;      // bound of a team member's wait for its next problem
 };
 
 __device__ inline const Args& batch_args(const CArgs* base, int i) {
   return *(const Args*)(base + i);
 }
 
+// Problem of class c's queue taken from the front (heavy end) or the back
+// (light end); -1 when the queue is empty.
+__device__ inline int queue_take(const BatchDesc& d, int c, bool front) {
+  unsigned long long* q = d.queue + c;
+  unsigned long long w = cload(q);
+  for (;;) {
+    const unsigned f = (unsigned)w, b = (unsigned)(w >> 32);
+    if (f >= b) return -1;
+    const unsigned long long nw = front ? (w + 1ull) : (w - (1ull << 32));
+    if (__hip_atomic_compare_exchange_strong(q, &w, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return d.order[d.class_first[c] + (int)(front ? f : b - 1)];
+  }
+}
+
+// Reset of every problem (one workgroup each) and, by workgroup 0, of the
+// class queues and the team slots.
 __global__ __launch_bounds__(256) void k_batch_init(BatchDesc d) {
-  const Args& a = batch_args(d.args, (int)blockIdx.x);
-  init_problem(a, a.fixed_m > 0 ? a.fixed_m : min(16, a.m_max));
+  const int i = (int)blockIdx.x;
+  const Args& a = batch_args(d.args, i);
+  int nflags = 0;
+  for (int c = 0; c < d.nclass; ++c)
+    nflags = max(nflags, batch_args(d.args, c * d.nprob + i).nwg * kFlagStride);
+  init_problem(a, a.fixed_m > 0 ? a.fixed_m : min(16, a.m_max), nflags);
+  if (i == 0) {
+    for (int c = kp_tid(); c < d.nclass; c += blockDim.x)
+      d.queue[c] = (unsigned long long)(d.class_first[c + 1] - d.class_first[c]) << 32;
+    for (int t = kp_tid(); t < d.nteams * 8; t += blockDim.x) d.slot[t] = 0ull;
+  }
 }
 
 template <typename TB>
@@ -240,13 +277,42 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
   __shared__ double lds[kLdsDoubles];
   __shared__ LeadLds lead;
   __shared__ Ctl cur, nxt;
-  __shared__ int ok;
+  __shared__ int ok, s_pi;
   __shared__ unsigned s_k;
   const int t = __builtin_amdgcn_readfirstlane(d.team_of_wg[blockIdx.x]);
   if (t < 0) return;
-  const int q1 = __builtin_amdgcn_readfirstlane(d.team_first[t + 1]);
-  for (int q = __builtin_amdgcn_readfirstlane(d.team_first[t]); q < q1; ++q) {
-    const Args& a = batch_args(d.args, __builtin_amdgcn_readfirstlane(d.order[q]));
+  const int c = __builtin_amdgcn_readfirstlane(d.team_class[t]);
+  const bool lead_wg = (int)blockIdx.x == __builtin_amdgcn_readfirstlane(d.team_wg0[t]);
+  unsigned long long* slot = d.slot + 8 * (size_t)t;
+  for (unsigned seq = 1;; ++seq) {
+    // the team's next problem: chosen by the leader, handed to the others
+    if (kp_tid() == 0) {
+      int pi = -1;
+      if (lead_wg) {
+        // own class first; then the light end of the classes of smaller
+        // teams (classes are ordered by decreasing team size): a problem is
+        // never moved to a team slower on it than the one planned for it
+        pi = queue_take(d, c, true);
+        for (int cc = c + 1; pi < 0 && cc < d.nclass; ++cc) pi = queue_take(d, cc, false);
+        cstore(slot, ((unsigned long long)seq << 32) | (unsigned)(pi + 1));
+      } else {
+        // bounded wait on the leader (it publishes as soon as the previous
+        // problem's last barrier is released)
+        const int64_t t0 = wall_clock64();
+        unsigned long long w = cload(slot);
+        while ((unsigned)(w >> 32) < seq) {
+          __builtin_amdgcn_s_sleep(1);
+          w = cload(slot);
+          if (wall_clock64() - t0 > d.wait_ticks) break;
+        }
+        pi = ((unsigned)(w >> 32) >= seq) ? (int)(unsigned)w - 1 : -1;
+      }
+      s_pi = pi;
+    }
+    __syncthreads();
+    const int pi = __builtin_amdgcn_readfirstlane(s_pi);
+    if (pi < 0) break;
+    const Args& a = batch_args(d.args, c * d.nprob + pi);
     if (kp_tid() == 0) {
       const unsigned long long w = cload(release_word(a));
       s_k = (unsigned)(w >> 32);
@@ -637,18 +703,20 @@ struct BatchCache {
   kp::Plan plan;
   int n_wg = 0;
   int nprob = 0;
-  std::vector<int> team_of_prob;
-  std::vector<size_t> prob_off;       // arena offset of each problem's basis and state vector
-  std::vector<size_t> team_off;       // arena offset of each team's shared buffers
-  std::vector<int64_t> team_hx;       // halo doubles per workgroup of each team
+  int nclass = 0;
+  std::vector<int> class_size;        // team size of class c
+  std::vector<int> class_wg0;         // first workgroup of class c's run of teams
+  std::vector<size_t> prob_off;       // arena offset of each problem's buffers
+  std::vector<int> prob_nwg;          // largest row-owning workgroup count over the classes
   std::vector<int64_t> flag_off;      // per problem, in unsigned
-  void* arena = nullptr;              // problem and team workspaces
+  void* arena = nullptr;              // per-problem buffers
   State* st = nullptr;                // [nprob]
   Pub* pub = nullptr;                 // [nprob]
   unsigned* sync = nullptr;           // [nprob][16]
   unsigned* flags = nullptr;
-  Args* d_args = nullptr;             // [nprob]
-  int* d_meta = nullptr;              // team_first | order | team_of_wg
+  Args* d_args = nullptr;             // [nclass][nprob]
+  int* d_meta = nullptr;              // order | class_first | team_of_wg | team_class | team_wg0
+  unsigned long long* d_q = nullptr;  // class queues, then team slots
   kp_info* d_info = nullptr;          // [nprob]
   std::vector<Args> hargs;
   kp::BatchDesc desc{};
@@ -662,7 +730,8 @@ void batch_free(BatchCache* b) {
   if (!b) return;
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
-  void* bufs[] = {b->arena, b->st, b->pub, b->sync, b->flags, b->d_args, b->d_meta, b->d_info};
+  void* bufs[] = {b->arena, b->st, b->pub, b->sync, b->flags, b->d_args, b->d_meta, b->d_q,
+                  b->d_info};
   for (void* x : bufs)
     if (x) hipFree(x);
   delete b;
@@ -675,14 +744,34 @@ int batch_occupancy(kp_ctx* ctx, int* occ) {
   return KP_OK;
 }
 
-// Team geometry of problem a on team t of the plan.
-void batch_geometry(const kp::Plan& pl, int t, Args* a) {
+// Geometry of a problem on the teams of one class (team size g, first
+// workgroup of the class's run of teams wg0).
+void batch_geometry(int g, int wg0, Args* a) {
   int rows, nw;
-  kp::plan_rows(a->nx, a->ny, pl.team_size[t], &rows, &nw);
+  kp::plan_rows(a->nx, a->ny, g, &rows, &nw);
   a->rows_per_wg = rows;
   a->nwg = nw;
-  a->nteam = pl.team_size[t];
-  a->wg0 = pl.team_wg0[t];
+  a->nteam = g;
+  a->wg0 = wg0;
+}
+
+// Sizes of a problem's own buffers (bytes, each 256-aligned): basis, state
+// vector, partial sums, halo rows, small-exponential scratch, tail values.
+struct ProbBufs {
+  size_t v, u, part, hx, ex, tx;
+  size_t total() const { return v + u + part + hx + ex + tx; }
+};
+
+ProbBufs prob_bufs(const Args& a, int nwg_max) {
+  const size_t esz = a.basis_f32 ? sizeof(float) : sizeof(double);
+  ProbBufs r;
+  r.v = align256((size_t)a.ld * (a.m_max + 2) * esz);
+  r.u = align256((size_t)a.ld * sizeof(double));
+  r.part = align256((size_t)nwg_max * kp::kKStride * sizeof(double));
+  r.hx = align256((size_t)nwg_max * a.nplanes * 2 * a.nx * sizeof(double));
+  r.ex = align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);
+  r.tx = align256(sizeof(double) * kp::kTailPad);
+  return r;
 }
 
 // New plan, allocations and graph for the problem set of `as` (validated).
@@ -701,77 +790,99 @@ int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp:
     return rc ? rc : KP_EHIP;
   }
   b->n_wg = ctx->ncu * occ;
-  b->plan = kp::make_plan(qs, b->n_wg, kp::PlanModel());
+  const kp::PlanModel model;
+  b->plan = kp::make_plan(qs, b->n_wg, model);
   const kp::Plan& pl = b->plan;
   const int nt = (int)pl.team_size.size();
-  b->team_of_prob.assign(np, -1);
-  for (int t = 0; t < nt; ++t)
-    for (int q = pl.team_first[t]; q < pl.team_first[t + 1]; ++q) b->team_of_prob[pl.order[q]] = t;
-  // per problem: basis and state vector; per team: partial sums, halo rows,
-  // small-exponential scratch and tail values, sized for the team's problems
-  const size_t esz = f32 ? sizeof(float) : sizeof(double);
-  std::vector<int64_t> hxm(nt, 0);
-  for (int i = 0; i < np; ++i) {
-    const int t = b->team_of_prob[i];
-    hxm[t] = std::max<int64_t>(hxm[t], (int64_t)as[i].nplanes * 2 * as[i].nx);
+  // classes: the runs of equal-size teams (the plan lays them out big, mid,
+  // single), each with the problems the plan gave its teams, heaviest first
+  std::vector<int> team_class(nt);
+  for (int t = 0; t < nt; ++t) {
+    if (t == 0 || pl.team_size[t] != pl.team_size[t - 1]) {
+      b->class_size.push_back(pl.team_size[t]);
+      b->class_wg0.push_back(pl.team_wg0[t]);
+    }
+    team_class[t] = (int)b->class_size.size() - 1;
   }
+  const int nc = (int)b->class_size.size();
+  b->nclass = nc;
+  std::vector<std::vector<int>> lists(nc);
+  for (int t = 0; t < nt; ++t)
+    for (int q = pl.team_first[t]; q < pl.team_first[t + 1]; ++q)
+      lists[team_class[t]].push_back(pl.order[q]);
+  std::vector<int> order, class_first(1, 0);
+  for (int c = 0; c < nc; ++c) {
+    const int g = b->class_size[c];
+    std::stable_sort(lists[c].begin(), lists[c].end(), [&](int x, int y) {
+      return kp::plan_time(qs[x], g, model) > kp::plan_time(qs[y], g, model);
+    });
+    order.insert(order.end(), lists[c].begin(), lists[c].end());
+    class_first.push_back((int)order.size());
+  }
+  // per-problem buffers, sized for the class that spreads the problem widest
+  b->prob_nwg.assign(np, 1);
+  for (int i = 0; i < np; ++i)
+    for (int c = 0; c < nc; ++c) {
+      Args g = as[i];
+      batch_geometry(b->class_size[c], b->class_wg0[c], &g);
+      b->prob_nwg[i] = std::max(b->prob_nwg[i], g.nwg);
+    }
   size_t off = 0;
   b->prob_off.assign(np, 0);
-  for (int i = 0; i < np; ++i) {
-    b->prob_off[i] = off;
-    off += align256((size_t)as[i].ld * (as[i].m_max + 2) * esz);       // V
-    off += align256((size_t)as[i].ld * sizeof(double));                // u
-  }
-  b->team_off.assign(nt, 0);
-  b->team_hx = hxm;
-  for (int t = 0; t < nt; ++t) {
-    b->team_off[t] = off;
-    if (hxm[t] == 0) continue;
-    const int g = pl.team_size[t];
-    off += align256((size_t)g * kp::kKStride * sizeof(double));          // part
-    off += align256((size_t)g * hxm[t] * sizeof(double));                // hx
-    off += align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);  // ex
-    off += align256(sizeof(double) * kp::kTailPad);                      // tx
-  }
   b->flag_off.assign(np, 0);
   int64_t nflags = 0;
-  std::vector<Args> hs = as;
   for (int i = 0; i < np; ++i) {
-    batch_geometry(pl, b->team_of_prob[i], &hs[i]);
+    b->prob_off[i] = off;
+    off += prob_bufs(as[i], b->prob_nwg[i]).total();
     b->flag_off[i] = nflags;
-    nflags += (int64_t)hs[i].nwg * kp::kFlagStride;
+    nflags += (int64_t)b->prob_nwg[i] * kp::kFlagStride;
   }
   hipError_t e = hipMalloc(&b->arena, std::max<size_t>(off, 256));
   if (e == hipSuccess) e = hipMalloc(&b->st, sizeof(State) * np);
   if (e == hipSuccess) e = hipMalloc(&b->pub, sizeof(Pub) * np);
   if (e == hipSuccess) e = hipMalloc(&b->sync, 64 * (size_t)np);
   if (e == hipSuccess) e = hipMalloc(&b->flags, sizeof(unsigned) * (size_t)std::max<int64_t>(nflags, 1));
-  if (e == hipSuccess) e = hipMalloc(&b->d_args, sizeof(Args) * np);
-  const size_t nmeta = (size_t)(nt + 1) + np + b->n_wg;
+  if (e == hipSuccess) e = hipMalloc(&b->d_args, sizeof(Args) * (size_t)nc * np);
+  const size_t nmeta = (size_t)np + (nc + 1) + b->n_wg + 2 * (size_t)nt;
   if (e == hipSuccess) e = hipMalloc(&b->d_meta, sizeof(int) * nmeta);
+  if (e == hipSuccess) e = hipMalloc(&b->d_q, sizeof(unsigned long long) * (nc + 8 * (size_t)nt));
   if (e == hipSuccess) e = hipMalloc(&b->d_info, sizeof(kp_info) * np);
   if (e != hipSuccess) {
     snprintf(ctx->err, sizeof(ctx->err), "batched workspace: %s", hipGetErrorString(e));
     batch_free(b);
     return KP_ENOMEM;
   }
+  // every team takes part, also one the plan left without problems: it
+  // takes problems from the other classes' queues
+  std::vector<int> team_of_wg(b->n_wg, -1);
+  for (int t = 0; t < nt; ++t)
+    for (int w = 0; w < pl.team_size[t]; ++w) team_of_wg[pl.team_wg0[t] + w] = t;
   std::vector<int> meta;
   meta.reserve(nmeta);
-  meta.insert(meta.end(), pl.team_first.begin(), pl.team_first.end());
-  meta.insert(meta.end(), pl.order.begin(), pl.order.end());
-  meta.insert(meta.end(), pl.team_of_wg.begin(), pl.team_of_wg.end());
+  meta.insert(meta.end(), order.begin(), order.end());
+  meta.insert(meta.end(), class_first.begin(), class_first.end());
+  meta.insert(meta.end(), team_of_wg.begin(), team_of_wg.end());
+  meta.insert(meta.end(), team_class.begin(), team_class.end());
+  meta.insert(meta.end(), pl.team_wg0.begin(), pl.team_wg0.end());
   e = hipMemcpy(b->d_meta, meta.data(), sizeof(int) * nmeta, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     batch_free(b);
     return hip_fail(ctx, e, "hipMemcpy(plan)");
   }
   b->desc.args = (const kp::CArgs*)(b->d_args);
-  b->desc.team_first = b->d_meta;
-  b->desc.order = b->d_meta + (nt + 1);
-  b->desc.team_of_wg = b->d_meta + (nt + 1) + np;
+  b->desc.order = b->d_meta;
+  b->desc.class_first = b->d_meta + np;
+  b->desc.team_of_wg = b->d_meta + np + (nc + 1);
+  b->desc.team_class = b->d_meta + np + (nc + 1) + b->n_wg;
+  b->desc.team_wg0 = b->d_meta + np + (nc + 1) + b->n_wg + nt;
+  b->desc.queue = b->d_q;
+  b->desc.slot = b->d_q + nc;
   b->desc.nprob = np;
-  // the graph: reset of every problem -> the persistent batched kernel
-  // (cooperative) -> the per-problem outcome records
+  b->desc.nclass = nc;
+  b->desc.nteams = nt;
+  b->desc.wait_ticks = ctx->wait_ticks;
+  // the graph: reset of every problem, the queues and the team slots -> the
+  // persistent batched kernel (cooperative) -> the per-problem outcome records
   hipGraphNode_t n1, n2, n3;
   void* a1[] = {&b->desc};
   void* a2[] = {&b->desc};
@@ -805,33 +916,31 @@ int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp:
   return KP_OK;
 }
 
-// Per-call Args of every problem: the caller's pointers and coefficients,
-// the team geometry and the team / problem buffers.
+// Per-call Args of every (class, problem): the caller's pointers and
+// coefficients, the class's team geometry and the problem's own buffers.
 void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ticks) {
-  const kp::Plan& pl = b->plan;
-  b->hargs = as;
-  for (int i = 0; i < b->nprob; ++i) {
-    Args& a = b->hargs[i];
-    const int t = b->team_of_prob[i];
-    batch_geometry(pl, t, &a);
-    const size_t esz = a.basis_f32 ? sizeof(float) : sizeof(double);
-    char* pbase = static_cast<char*>(b->arena) + b->prob_off[i];
-    a.V = pbase;
-    a.u = reinterpret_cast<double*>(pbase + align256((size_t)a.ld * (a.m_max + 2) * esz));
-    char* base = static_cast<char*>(b->arena) + b->team_off[t];
-    const int g = pl.team_size[t];
-    a.part = reinterpret_cast<double*>(base);
-    base += align256((size_t)g * kp::kKStride * sizeof(double));
-    a.hx = reinterpret_cast<double*>(base);
-    base += align256((size_t)g * b->team_hx[t] * sizeof(double));
-    a.ex = reinterpret_cast<double*>(base);
-    base += align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);
-    a.tx = reinterpret_cast<double*>(base);
+  const int np = b->nprob;
+  b->hargs.resize((size_t)b->nclass * np);
+  for (int i = 0; i < np; ++i) {
+    Args a = as[i];
+    const ProbBufs z = prob_bufs(a, b->prob_nwg[i]);
+    char* base = static_cast<char*>(b->arena) + b->prob_off[i];
+    a.V = base;
+    a.u = reinterpret_cast<double*>(base + z.v);
+    a.part = reinterpret_cast<double*>(base + z.v + z.u);
+    a.hx = reinterpret_cast<double*>(base + z.v + z.u + z.part);
+    a.ex = reinterpret_cast<double*>(base + z.v + z.u + z.part + z.hx);
+    a.tx = reinterpret_cast<double*>(base + z.v + z.u + z.part + z.hx + z.ex);
     a.st = b->st + i;
     a.pub = b->pub + i;
     a.sync = b->sync + 16 * (size_t)i;
     a.flags = b->flags + b->flag_off[i];
     a.wait_ticks = wait_ticks;
+    for (int c = 0; c < b->nclass; ++c) {
+      Args& r = b->hargs[(size_t)c * np + i];
+      r = a;
+      batch_geometry(b->class_size[c], b->class_wg0[c], &r);
+    }
   }
 }
 
@@ -1077,7 +1186,7 @@ int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops, const dou
   }
   BatchCache* b = ctx->batch;
   batch_fill_args(b, as, ctx->wait_ticks);
-  KP_HIP(ctx, hipMemcpyAsync(b->d_args, b->hargs.data(), sizeof(Args) * nprob,
+  KP_HIP(ctx, hipMemcpyAsync(b->d_args, b->hargs.data(), sizeof(Args) * b->hargs.size(),
                              hipMemcpyHostToDevice, ctx->stream));
   KP_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
   ctx->have_begin = 0;
