@@ -254,3 +254,17 @@ def test_full_size_adjoint_workload():
     assert e_y <= 10 * pr.tol
     assert max(e_B) <= 1e-8
     assert abs(gnu - gnu_ref) <= 1e-7 * abs(gnu_ref)
+
+
+def test_tangent_fp32_basis():
+    """The tangent solve with the FP32 basis, against the oracle's tangent."""
+    pr = W.random_problem(49, kind=W.OP_ADR, nx=96, ny=80, p=2, h=0.05, with_diag=True)
+    op = kp.Operator.from_host(pr.op)
+    with kp.Context(basis="f32") as ctx:
+        y, dy, info = ctx.phi_combo_tangent(op, dev_dir(op, *DIRECTION), dev_B(pr.B), pr.h,
+                                            tol=1e-6, m_max=32, info=True)
+    ry, rdy, _ = adjoint.phi_combo_tangent(pr.op, host_dir(pr.op, *DIRECTION), pr.B, pr.h, 2,
+                                           tol=1e-12, m_max=32, orth="hybrid")
+    e_y, e_dy = rel(y.cpu().numpy(), ry), rel(dy.cpu().numpy(), rdy)
+    say(f"  fp32 tangent: rel y {e_y:.2e} dy {e_dy:.2e}")
+    assert info["status"] == 0 and e_y <= 1e-5 and e_dy <= 1e-5

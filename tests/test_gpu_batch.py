@@ -179,3 +179,43 @@ def test_full_size_uneven_batch_against_closed_form():
         worst = max(worst, rel(y.cpu().numpy(), closed_form.adr_phi_combo(q.op, q.B, q.h, q.p)))
     say(f"  arnoldi steps {steps}, worst rel err vs closed form {worst:.2e}")
     assert worst <= 10 * 1e-8
+
+
+def test_batched_edge_cases():
+    """One problem; h = 0 (out = b_0); p = 0; a non-finite input reported for
+    its problem only; a zero start vector."""
+    probs = _mixed(600)[:4]
+    devs = [dev(pr) for pr in probs]
+    ops, Bs = [d[0] for d in devs], [d[1].clone() for d in devs]
+    with kp.Context() as ctx:
+        (y,), (inf,) = ctx.phi_combo_batched(ops[:1], Bs[:1], [probs[0].h], tol=1e-10, m_max=32,
+                                             info=True)
+        ref, _ = krylov.phi_combo(probs[0].op, probs[0].B, probs[0].h, probs[0].p, tol=1e-10,
+                                  m_max=32, orth="hybrid")
+        assert inf["status"] == 0 and rel(y.cpu().numpy(), ref) <= FP64_TOL
+        Bs[1][0, 5] = float("nan")
+        Bs[2].zero_()
+        hs = [0.0, probs[1].h, probs[2].h, probs[3].h]
+        ys, infos = ctx.phi_combo_batched(ops, Bs, hs, tol=1e-10, m_max=32, info=True)
+    assert infos[0]["status"] == 0 and np.array_equal(ys[0].cpu().numpy(), probs[0].B[:, 0])
+    assert infos[1]["status"] == kp._lib.KP_STATUS_NONFINITE
+    assert infos[2]["status"] == 0 and not ys[2].abs().any()
+    ref3, _ = krylov.phi_combo(probs[3].op, probs[3].B, probs[3].h, probs[3].p, tol=1e-10,
+                               m_max=32, orth="hybrid")
+    assert infos[3]["status"] == 0 and rel(ys[3].cpu().numpy(), ref3) <= FP64_TOL
+
+
+def test_batched_fp32_basis():
+    """The FP32-basis form through the batched call, against the FP64 batched
+    call and the oracle (mixed kinds, adaptive)."""
+    probs = _mixed(700)
+    devs = [dev(pr) for pr in probs]
+    ops, Bs, hs = [d[0] for d in devs], [d[1] for d in devs], [pr.h for pr in probs]
+    with kp.Context(basis="f32") as ctx:
+        y32, inf32 = ctx.phi_combo_batched(ops, Bs, hs, tol=1e-6, m_max=32, info=True)
+    for pr, y, inf in zip(probs, y32, inf32):
+        ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, tol=1e-12, m_max=32)
+        e = rel(y.cpu().numpy(), ref)
+        say(f"  fp32 batched kind={pr.op.kind} {pr.op.nx}x{pr.op.ny}: rel err {e:.2e}")
+        assert inf["status"] == 0 and inf["t_end"] == pr.h
+        assert e <= 1e-5
