@@ -12,29 +12,46 @@
 namespace kp {
 
 // dst[k] = sum over workgroups of part[w][k], k < nslot; fixed order.
-// Thread (g, l) of kRg groups sums slot l over the workgroups w = g (mod kRg);
-// its coherent loads are all issued before they are consumed, so the
-// reduction costs about one memory latency per 64 workgroups.
-// grp: LDS scratch of kRg * kKStride doubles.
-constexpr int kRg = 4;
+// Thread (g, l) of kRg groups sums the slot pair (kb + 2l, kb + 2l + 1) over
+// the workgroups w = g (mod kRg) with 16-byte coherent loads (buffer loads
+// with the agent-scope coherence bit, as the 8-byte coherent loads carry;
+// rows past nwg lie beyond the descriptor's range and read as zero), all
+// issued before they are consumed: about one memory latency per round of
+// 128 slots.  grp: LDS scratch of kRg * kKStride doubles.
+constexpr int kRg = 8;
+constexpr int kBufWord3 = 0x00020000;   // raw buffer descriptor, gfx9 family
+constexpr int kCoherentAux = 16;        // sc1: agent-scope coherent load
+
+__device__ inline double lo_double(unsigned x, unsigned y) {
+  return __builtin_bit_cast(double, (unsigned long long)x | ((unsigned long long)y << 32));
+}
+
 __device__ __attribute__((always_inline)) inline void reduce_partials(const Args& a, int nslot, double* dst, double* grp) {
-  constexpr int kS = kThreads / kRg;
-  const int g = kp_tid() / kS, l = kp_tid() % kS;
-  for (int kb = 0; kb < nslot; kb += kS) {
-    const int k = kb + l;
+  constexpr int kP = kThreads / kRg;   // slot pairs per round
+  constexpr int kQ = 32;               // workgroups per thread per pass
+  const int g = kp_tid() / kP, l = kp_tid() % kP;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      a.part, (short)0, a.nwg * kKStride * (int)sizeof(double), kBufWord3);
+  for (int kb = 0; kb < nslot; kb += 2 * kP) {
+    const int k = kb + 2 * l;
     if (k < nslot) {
-      double s = 0.0;
-      for (int w0 = 0; w0 < a.nwg; w0 += 64 * kRg) {
-        double v[64];
+      double sx = 0.0, sy = 0.0;
+      for (int w0 = 0; w0 < a.nwg; w0 += kQ * kRg) {
+        decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0)) v[kQ];
 #pragma unroll
-        for (int q = 0; q < 64; ++q) {
+        for (int q = 0; q < kQ; ++q) {
           const int w = w0 + g + kRg * q;
-          v[q] = (w < a.nwg) ? cload(a.part + (int64_t)w * kKStride + k) : 0.0;
+          v[q] = __builtin_amdgcn_raw_buffer_load_b128(
+              rs, (w * kKStride + k) * (int)sizeof(double), 0, kCoherentAux);
         }
 #pragma unroll
-        for (int q = 0; q < 64; ++q) s += v[q];
+        for (int q = 0; q < kQ; ++q) {
+          sx += lo_double(v[q][0], v[q][1]);
+          sy += lo_double(v[q][2], v[q][3]);
+        }
       }
-      grp[g * kKStride + k] = s;
+      grp[g * kKStride + k] = sx;
+      grp[g * kKStride + k + 1] = sy;
     }
   }
   __syncthreads();
