@@ -184,6 +184,36 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
                          double* out, double* dout, kp_info* info);
 
 /*
+ * Gradients of a loss L(y) of the phi combination y = sum_k h^k phi_k(h A) b_k
+ * (kp_phi_combo's arguments A, B, p, ldb, h, tol, m_max), given g = dL/dy:
+ *   grad_B[:, k]  = h^k phi_k(h A^T) g,  k = 0..p: the phi combination of the
+ *                   transposed operator with B = [0, ..., 0, g] (the phi
+ *                   functions of A^T are the transposes of those of A);
+ *                   p + 1 solves as in kp_phi_combo.
+ *   grad_coef[c]  = <g, dy/dtheta_c> for every bit c of coef_mask, theta =
+ *                   (nu, ax, ay, react) (bits 0..3): one kp_phi_combo_tangent
+ *                   solve with the unit direction of that coefficient
+ *                   (dA = Lap, -Dx, -Dy or I; transposed with A), then a
+ *                   fixed-order device inner product.
+ *   g       : device, N doubles.
+ *   grad_B  : device, N x (p+1) column-major with leading dimension
+ *             ldgb >= N, or NULL (no B-gradient); disjoint from B and g.
+ *   grad_coef: device, 4 doubles (entries of unset bits untouched), NULL
+ *             only when coef_mask = 0.
+ *   Coefficient gradients need KP_OP_ADR or KP_OP_ALLEN_CAHN and 2p <= KP_PMAX.
+ *   info    : optional; when non-NULL every solve is synchronised and info
+ *             gets the worst status and the summed work of all the solves.
+ * Asynchronous unless info is requested; no tape of the forward call is
+ * needed (the solves recompute what they need).  The context keeps a
+ * workspace of (p + 3) N doubles for it.
+ * Errors: KP_EINVAL, KP_EUNSUPPORTED, KP_ENOMEM, KP_EHIP.
+ */
+int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
+                          int64_t ldb, double h, double tol, int32_t m_max, const double* g,
+                          double* grad_B, int64_t ldgb, int32_t coef_mask, double* grad_coef,
+                          kp_info* info);
+
+/*
  * Many independent phi combinations in one call (the uneven-batch form):
  *     out[i][0..N_i) = sum_{k=0}^{p_i} h_i^k phi_k(h_i A_i) b_{i,k},  i < nprob,
  * each computed exactly as kp_phi_combo computes it (Section 3's hybrid

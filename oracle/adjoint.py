@@ -46,7 +46,7 @@ def phi_combo_tangent(op, dop, B: np.ndarray, h: float, p: int, **kw):
 def grad_B(op, g: np.ndarray, h: float, p: int, phi_combo, **kw) -> np.ndarray:
     """Columns h^k phi_k(h A^T) g, k = 0..p, by the given phi-combination
     routine (Krylov or closed form) applied to the transposed operator."""
-    opt = op.with_transpose()
+    opt = op.with_transpose(not op.transpose)
     n = op.n
     G = np.zeros((n, p + 1))
     for k in range(p + 1):

@@ -8,11 +8,11 @@
   (the transpose flips the sign of the advection term).  Hence
       sum_k h^k phi_k(hA) b_k = sum_k h^k IDFT(phi_k(h lambda) DFT(b_k)).
 * Diagonal A: phi_k acts elementwise (oracle.phi.phi_combo_diag).
-* Derivative in the diffusion coefficient: d lambda / d nu is the Laplacian's
-  eigenvalue, and d/dz phi_k(z) = phi_k(z) - k phi_{k+1}(z) (differentiate
-  the integral definition: the factor (1 - s) splits into phi_k and
-  k phi_{k+1}), so d/dnu h^k phi_k(h lambda) = h^{k+1} (phi_k - k phi_{k+1})
-  (h lambda) dlambda/dnu.
+* Derivative along a coefficient direction (nu, ax, ay, r): d lambda is the
+  eigenvalue of the direction's stencil (for nu the Laplacian's), and
+  d/dz phi_k(z) = phi_k(z) - k phi_{k+1}(z) (differentiate the integral
+  definition: the factor (1 - s) splits into phi_k and k phi_{k+1}), so
+  d h^k phi_k(h lambda) = h^{k+1} (phi_k - k phi_{k+1})(h lambda) d lambda.
 """
 from __future__ import annotations
 
@@ -62,8 +62,19 @@ def adr_laplacian_eigenvalues(op) -> np.ndarray:
 
 def adr_phi_combo_dnu(op, B: np.ndarray, h: float, p: int) -> np.ndarray:
     """d/dnu of sum_k h^k phi_k(h A(nu)) b_k for the constant-coefficient ADR."""
+    return _adr_phi_combo_deriv(op, adr_laplacian_eigenvalues(op), B, h, p)
+
+
+def adr_phi_combo_deriv(op, dop, B: np.ndarray, h: float, p: int) -> np.ndarray:
+    """Derivative of sum_k h^k phi_k(h A) b_k along the constant-coefficient
+    ADR direction dop (same grid and transpose flag as op): A and dA share
+    the DFT eigenvectors, and the eigenvalues of dA are those of an ADR
+    operator with dop's coefficients (linear in them)."""
+    return _adr_phi_combo_deriv(op, adr_eigenvalues(dop), B, h, p)
+
+
+def _adr_phi_combo_deriv(op, dlam, B, h, p):
     lam = adr_eigenvalues(op)
-    dlam = adr_laplacian_eigenvalues(op)
     acc = np.zeros((op.ny, op.nx), dtype=complex)
     for k in range(p + 1):
         bk = B[:, k].reshape(op.ny, op.nx)

@@ -150,6 +150,34 @@ class Context:
         _lib.check(rc, self.h)
         return (out, dout, inf.as_dict()) if info else (out, dout)
 
+    COEFS = ("nu", "ax", "ay", "react")
+
+    def phi_combo_backward(self, op: Operator, B, h: float, g, tol: float = 1e-8,
+                           m_max: int = 64, want_B: bool = True, coefs=("nu",),
+                           info: bool = False):
+        """Gradients of a loss of y = phi_combo(op, B, h) given g = dL/dy:
+        (grad_B (p+1, N) or None, grad_coef (4,) device tensor with the entries
+        of `coefs` among ("nu", "ax", "ay", "react") filled)."""
+        torch = _torch()
+        n = op.n
+        p, ldb = self._check_B(B, n)
+        if g.dtype != torch.float64 or not g.is_cuda or not g.is_contiguous() or g.numel() != n:
+            raise ValueError("g must be a contiguous float64 device vector of N")
+        mask = 0
+        for c in coefs:
+            mask |= 1 << self.COEFS.index(c)
+        gB = torch.empty((p + 1, n), dtype=torch.float64, device=B.device) if want_B else None
+        gc = torch.zeros(4, dtype=torch.float64, device=B.device)
+        opc = op.c_struct()
+        inf = KpInfo() if info else None
+        rc = self.lib.kp_phi_combo_backward(
+            self.h, ctypes.byref(opc), ctypes.c_void_p(B.data_ptr()), p, ldb, float(h),
+            float(tol), int(m_max), ctypes.c_void_p(g.data_ptr()),
+            ctypes.c_void_p(gB.data_ptr()) if gB is not None else None, n, mask,
+            ctypes.c_void_p(gc.data_ptr()), ctypes.byref(inf) if inf is not None else None)
+        _lib.check(rc, self.h)
+        return (gB, gc, inf.as_dict()) if info else (gB, gc)
+
     def phi_combo_batched(self, ops, Bs, hs, tol: float = 1e-8, m_max: int = 64, outs=None,
                           info: bool = False):
         """Independent phi combinations in one call: outs[i] = sum_k hs[i]^k

@@ -25,7 +25,7 @@ BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
 
 # Exported symbols (every function declared in the header).
 SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_tangent",
-           "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
+           "kp_phi_combo_backward", "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
            "kp_strerror", "kp_last_error", "kp_version")
 
@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_phi_combo_tangent.argtypes = [P, ctypes.POINTER(KpOp), ctypes.POINTER(KpOp), P, I32,
                                          I64, D, D, I32, P, P, ctypes.POINTER(KpInfo)]
     PI32, PD = ctypes.POINTER(I32), ctypes.POINTER(D)
+    lib.kp_phi_combo_backward.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, D, D, I32, P, P, I64,
+                                          I32, P, ctypes.POINTER(KpInfo)]
     lib.kp_phi_combo_batched.argtypes = [P, I32, ctypes.POINTER(KpOp), ctypes.POINTER(P), PI32,
                                          ctypes.POINTER(I64), PD, D, I32, ctypes.POINTER(P),
                                          ctypes.POINTER(KpInfo)]

@@ -1,25 +1,27 @@
 """Gradients of the phi combination (torch.autograd), computed by the library.
 
-    y = sum_{k=0}^{p} h^k phi_k(h A(nu)) b_k,    A(nu) = nu Lap + (the rest of A)
+    y = sum_{k=0}^{p} h^k phi_k(h A(theta)) b_k,
+    A(theta) = nu Lap - ax Dx - ay Dy + react I (+ the operator's fields)
 
-For an upstream gradient g = dL/dy:
+For an upstream gradient g = dL/dy, kp_phi_combo_backward returns
 
   * dL/db_k = h^k phi_k(h A^T) g: one Krylov solve with the transposed
-    operator per k (kp_phi_combo with transpose set, B = [0, ..., 0, g]); this
-    is the adjoint of the map b_k -> y (the phi functions of A^T are the
-    transposes of those of A).
-  * dL/dnu = <g, dy/dnu>, with dy/dnu from one solve of the block operator
-    [[Atilde, Etilde], [0, Atilde]], Etilde = [[Lap, 0], [0, 0]]
-    (kp_phi_combo_tangent: the Frechet derivative of the exponential of the
-    augmented matrix of Section 2.1 in the direction of the operator change).
+    operator per k (B = [0, ..., 0, g]); the adjoint of the map b_k -> y, as
+    the phi functions of A^T are the transposes of those of A;
+  * dL/dtheta_c = <g, dy/dtheta_c> for every coefficient that requires a
+    gradient: one solve of the block operator [[Atilde, Etilde], [0, Atilde]],
+    Etilde = [[dA/dtheta_c, 0], [0, 0]] (the Frechet derivative of the
+    exponential of Section 2.1's augmented matrix in the direction of the
+    coefficient), and a fixed-order device inner product.
 
-Every solve runs in the HIP library; torch only holds the tensors and forms
-the chain-rule inner product.
+Every solve and the inner products run in the HIP library; torch only holds
+the tensors.
 """
 from __future__ import annotations
 
-
 from . import Context, Operator
+
+COEFS = ("nu", "ax", "ay", "react")
 
 
 def _with(op: Operator, **kw) -> Operator:
@@ -52,8 +54,10 @@ def _fn():
 
     class PhiComboFn(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, B, nu, op, h, tol, m_max, ctx_kw):
-            opn = _with(op, nu=float(nu))
+        def forward(ctx, B, nu, ax, ay, react, op, h, tol, m_max, ctx_kw):
+            vals = {name: float(t) for name, t in zip(COEFS, (nu, ax, ay, react))
+                    if t is not None}
+            opn = _with(op, **vals)
             y = _context(ctx_kw).phi_combo(opn, B.contiguous(), h, tol=tol, m_max=m_max)
             ctx.save_for_backward(B)
             ctx.op, ctx.h, ctx.tol, ctx.m_max, ctx.ctx_kw = opn, h, tol, m_max, ctx_kw
@@ -62,25 +66,14 @@ def _fn():
         @staticmethod
         def backward(ctx, g):
             (B,) = ctx.saved_tensors
-            op, h, tol, m_max = ctx.op, ctx.h, ctx.tol, ctx.m_max
-            g = g.contiguous()
-            grad_B = grad_nu = None
-            c = _context(ctx.ctx_kw)
-            if ctx.needs_input_grad[0]:
-                opt = _with(op, transpose=not op.transpose)
-                p = B.shape[0] - 1
-                grad_B = torch.empty_like(B)
-                for k in range(p + 1):
-                    Bk = torch.zeros((k + 1, B.shape[1]), dtype=B.dtype, device=B.device)
-                    Bk[k] = g
-                    c.phi_combo(opt, Bk, h, tol=tol, m_max=m_max, out=grad_B[k])
-            if ctx.needs_input_grad[1]:
-                dop = _with(op, nu=1.0, ax=0.0, ay=0.0, react=0.0, field0=None,
-                            field1=None)
-                _, dy = c.phi_combo_tangent(op, dop, B.contiguous(), h, tol=tol,
-                                            m_max=m_max)
-                grad_nu = torch.dot(g, dy).reshape(())
-            return grad_B, grad_nu, None, None, None, None, None
+            want_B = ctx.needs_input_grad[0]
+            coefs = [name for name, need in zip(COEFS, ctx.needs_input_grad[1:5]) if need]
+            gB, gc = _context(ctx.ctx_kw).phi_combo_backward(
+                ctx.op, B.contiguous(), ctx.h, g.contiguous(), tol=ctx.tol, m_max=ctx.m_max,
+                want_B=want_B, coefs=coefs)
+            grads = [gc[COEFS.index(name)].reshape(()) if name in coefs else None
+                     for name in COEFS]
+            return (gB, *grads, None, None, None, None, None)
 
     return PhiComboFn
 
@@ -95,14 +88,16 @@ def release_contexts() -> None:
     _CTX.clear()
 
 
-def phi_combo(B, nu, op: Operator, h: float, tol: float = 1e-8, m_max: int = 64, **ctx_kw):
-    """Differentiable phi combination: B (p+1, N) and nu (0-dim tensor) may
-    require gradients; op supplies the grid and the other coefficients.
-    ctx_kw are Context options (orth, basis, fixed_m, fixed_substeps, ...);
-    the solves run on torch's current stream."""
+def phi_combo(B, nu, op: Operator, h: float, tol: float = 1e-8, m_max: int = 64, ax=None,
+              ay=None, react=None, **ctx_kw):
+    """Differentiable phi combination: B (p+1, N) and the coefficient tensors
+    nu, ax, ay, react (0-dim; None keeps op's value) may require gradients;
+    op supplies the grid, the fields and the other coefficients.  ctx_kw are
+    Context options (orth, basis, fixed_m, fixed_substeps, ...); the solves
+    run on torch's current stream."""
     if "stream" in ctx_kw:
         raise ValueError("phi_combo runs on torch's current stream; do not pass stream")
     global _FN
     if _FN is None:
         _FN = _fn()
-    return _FN.apply(B, nu, op, h, tol, m_max, ctx_kw)
+    return _FN.apply(B, nu, ax, ay, react, op, h, tol, m_max, ctx_kw)

@@ -360,6 +360,33 @@ __global__ __launch_bounds__(64) void k_batch_info(BatchDesc d, kp_info* out) {
   out[i] = r;
 }
 
+// <x, y> in a fixed order (the gradient of the loss in an operator
+// coefficient): 256 workgroups each reduce one contiguous chunk, then one
+// workgroup sums the 256 partials.
+constexpr int kDotBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* x, const double* y, int64_t n,
+                                                     double* part) {
+  __shared__ double red[4];
+  const int64_t chunk = (n + kDotBlocks - 1) / kDotBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double s = 0.0;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += 256) s += x[e] * y[e];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* part, double* out) {
+  __shared__ double red[4];
+  double s = part[threadIdx.x];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -399,6 +426,8 @@ struct kp_ctx {
   Pub* pub = nullptr;
   double* ex = nullptr;
   double* tx = nullptr;
+  double* aux = nullptr;           // backward: [0...0 g] matrix, tangent outputs, dot partials
+  size_t aux_bytes = 0;
   int occ[2] = {-1, -1};
   Args last{};
   int have_begin = 0;
@@ -993,7 +1022,7 @@ int kp_destroy(kp_ctx* ctx) {
   if (ctx->ncu > 0) hipStreamSynchronize(ctx->stream);
   batch_free(ctx->batch);
   void* bufs[] = {ctx->V,  ctx->u,    ctx->part, ctx->hx, ctx->flags,
-                  ctx->st, ctx->pub, ctx->sync, ctx->ex, ctx->tx};
+                  ctx->st, ctx->pub, ctx->sync, ctx->ex, ctx->tx, ctx->aux};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete ctx;
@@ -1056,6 +1085,84 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
   ctx->last = a;
   ctx->have_begin = 0;
   if (info) return fill_info(ctx, info);
+  return KP_OK;
+}
+
+int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
+                          int64_t ldb, double h, double tol, int32_t m_max, const double* g,
+                          double* grad_B, int64_t ldgb, int32_t coef_mask, double* grad_coef,
+                          kp_info* info) {
+  if (!ctx || !A || !B || !g) return KP_EINVAL;
+  if (coef_mask < 0 || coef_mask > 15 || (coef_mask && !grad_coef)) return KP_EINVAL;
+  if (!grad_B && !coef_mask) return KP_EINVAL;
+  Args a;
+  int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, nullptr, false, &a);
+  if (rc) return rc;
+  const int64_t N = a.N;
+  if (grad_B && ldgb < N) return KP_EINVAL;
+  if (coef_mask && A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) return KP_EUNSUPPORTED;
+  if ((rc = device_setup(ctx))) return rc;
+  // aux: W = [0_1 .. 0_p | g] (N x (p+1)), then y, dy (N each), dot partials
+  const size_t need = sizeof(double) * ((size_t)(p + 3) * N + kp::kDotBlocks);
+  if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->aux), &ctx->aux_bytes, need))) return rc;
+  double* W = ctx->aux;
+  double* y = W + (size_t)(p + 1) * N;
+  double* dy = y + N;
+  double* part = dy + N;
+  if (grad_B && (overlaps(grad_B, (size_t)ldgb * (p + 1) * sizeof(double), g, N * sizeof(double)) ||
+                 overlaps(grad_B, (size_t)ldgb * (p + 1) * sizeof(double), B,
+                          (size_t)ldb * (p + 1) * sizeof(double))))
+    return KP_EINVAL;
+  int worst = KP_STATUS_OK;
+  auto track = [&](const kp_info* r) {   // worst status, summed work
+    if (r->status > worst) worst = r->status;
+    info->substeps += r->substeps;
+    info->rejected += r->rejected;
+    info->arnoldi_steps += r->arnoldi_steps;
+    info->expm_evals += r->expm_evals;
+    info->n_fallback += r->n_fallback;
+    info->breakdowns += r->breakdowns;
+    info->err_max = std::max(info->err_max, r->err_max);
+    info->t_end = r->t_end;
+  };
+  kp_info tmp;
+  kp_info* ip = info ? &tmp : nullptr;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (grad_B) {
+    // dL/db_k = h^k phi_k(h A^T) g: the phi combination of A^T with
+    // B_k = [0, ..., 0, g] (k zero columns), a view of W from column p - k
+    kp_op At = *A;
+    At.transpose = A->transpose ? 0 : 1;
+    if (p > 0) KP_HIP(ctx, hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * N, ctx->stream));
+    KP_HIP(ctx, hipMemcpyAsync(W + (size_t)p * N, g, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    for (int k = 0; k <= p; ++k) {
+      if ((rc = kp_phi_combo(ctx, &At, W + (size_t)(p - k) * N, k, N, h, tol, m_max,
+                             grad_B + (size_t)k * ldgb, ip)))
+        return rc;
+      if (info) track(ip);
+    }
+  }
+  // dL/dtheta = <g, dy/dtheta>: one tangent solve per requested coefficient
+  for (int c = 0; c < 4; ++c) {
+    if (!(coef_mask & (1 << c))) continue;
+    kp_op dA = *A;
+    dA.field0 = dA.field1 = nullptr;
+    dA.nu = c == 0 ? 1.0 : 0.0;
+    dA.ax = c == 1 ? 1.0 : 0.0;
+    dA.ay = c == 2 ? 1.0 : 0.0;
+    dA.react = c == 3 ? 1.0 : 0.0;
+    if ((rc = kp_phi_combo_tangent(ctx, A, &dA, B, p, ldb, h, tol, m_max, y, dy, ip))) return rc;
+    if (info) track(ip);
+    hipLaunchKernelGGL(kp::k_dot_partial, dim3(kp::kDotBlocks), dim3(256), 0, ctx->stream, g, dy,
+                       N, part);
+    hipLaunchKernelGGL(kp::k_dot_final, dim3(1), dim3(256), 0, ctx->stream, part, grad_coef + c);
+    KP_HIP(ctx, hipGetLastError());
+  }
+  if (info) {
+    KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    info->status = worst;
+  }
   return KP_OK;
 }
 

@@ -268,3 +268,72 @@ def test_tangent_fp32_basis():
     e_y, e_dy = rel(y.cpu().numpy(), ry), rel(dy.cpu().numpy(), rdy)
     say(f"  fp32 tangent: rel y {e_y:.2e} dy {e_dy:.2e}")
     assert info["status"] == 0 and e_y <= 1e-5 and e_dy <= 1e-5
+
+
+# ---- the C-ABI backward (kp_phi_combo_backward) --------------------------------
+
+UNITS = {"nu": (1.0, 0, 0, 0), "ax": (0, 1.0, 0, 0), "ay": (0, 0, 1.0, 0), "react": (0, 0, 0, 1.0)}
+
+
+@pytest.mark.parametrize("tr", [False, True])
+def test_backward_entry_all_coefficients_against_closed_form(tr):
+    op_h = W.Operator(kind=W.OP_ADR, nx=64, ny=48, nu=0.02, ax=1.0, ay=-0.5, react=-0.2,
+                      transpose=tr)
+    rng = np.random.default_rng(51)
+    Bh = rng.standard_normal((op_h.n, 3))
+    gh = rng.standard_normal(op_h.n)
+    h, p = 0.05, 2
+    op = kp.Operator.from_host(op_h)
+    with kp.Context() as ctx:
+        gB, gc, info = ctx.phi_combo_backward(op, dev_B(Bh), h, torch.as_tensor(gh, device="cuda"),
+                                              tol=1e-12, m_max=48, coefs=tuple(UNITS), info=True)
+    gB = gB.cpu().numpy().T
+    gc = gc.cpu().numpy()
+    gB_ref = adjoint.grad_B(op_h, gh, h, p, closed_form.adr_phi_combo)
+    e_B = [rel(gB[:, k], gB_ref[:, k]) for k in range(p + 1)]
+    say(f"  T={tr} grad_B per column {[f'{e:.1e}' for e in e_B]} steps {info['arnoldi_steps']}")
+    assert info["status"] == 0 and max(e_B) <= 1e-9
+    for c, name in enumerate(UNITS):
+        ref = float(gh @ closed_form.adr_phi_combo_deriv(op_h, host_dir(op_h, *UNITS[name]), Bh,
+                                                         h, p))
+        say(f"  d/d{name}: {gc[c]:.12e} ref {ref:.12e}")
+        assert abs(gc[c] - ref) <= 1e-8 * abs(ref)
+
+
+def test_backward_entry_brusselator_grad_B_and_rejections():
+    """B-gradient through the 2-species Jacobian against the oracle's
+    transposed Krylov solves; coefficient gradients are refused for it."""
+    pr = W.random_problem(52, kind=W.OP_BRUSSELATOR, nx=40, ny=36, p=2, h=0.01, nu=0.02)
+    op = kp.Operator.from_host(pr.op)
+    rng = np.random.default_rng(53)
+    gh = rng.standard_normal(pr.op.n)
+    g = torch.as_tensor(gh, device="cuda")
+    with kp.Context() as ctx:
+        gB, _ = ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, tol=1e-12, m_max=48, coefs=())
+        with pytest.raises(RuntimeError, match=r"\[-4\]"):
+            ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, coefs=("nu",))
+        with pytest.raises(RuntimeError, match=r"\[-1\]"):   # nothing asked for
+            ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, want_B=False, coefs=())
+    gB_ref = adjoint.grad_B(pr.op, gh, pr.h, 2, krylov.phi_combo, tol=1e-12, m_max=48,
+                            orth="hybrid")
+    assert rel(gB.cpu().numpy().T, gB_ref) <= 1e-9
+
+
+def test_autograd_advection_and_reaction_coefficients():
+    op_h = W.Operator(kind=W.OP_ADR, nx=48, ny=40, nu=0.01, ax=0.8, ay=0.3, react=0.4)
+    rng = np.random.default_rng(54)
+    Bh = rng.standard_normal((op_h.n, 2))
+    wh = rng.standard_normal(op_h.n)
+    h, p = 0.1, 1
+    op = kp.Operator.from_host(op_h)
+    B = dev_B(Bh)
+    t = {k: torch.tensor(getattr(op_h, k), dtype=torch.float64, device="cuda",
+                         requires_grad=True) for k in ("ax", "ay", "react")}
+    y = kpa.phi_combo(B, None, op, h, tol=1e-12, m_max=48, ax=t["ax"], ay=t["ay"],
+                      react=t["react"])
+    (torch.as_tensor(wh, device="cuda") @ y).backward()
+    for name in ("ax", "ay", "react"):
+        ref = float(wh @ closed_form.adr_phi_combo_deriv(op_h, host_dir(op_h, *UNITS[name]), Bh,
+                                                         h, p))
+        say(f"  autograd d/d{name}: {float(t[name].grad):.12e} ref {ref:.12e}")
+        assert abs(float(t[name].grad) - ref) <= 1e-8 * abs(ref)

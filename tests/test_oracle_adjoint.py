@@ -99,8 +99,9 @@ def test_tangent_adaptive_matches_closed_form():
     assert _rel(dy, closed_form.adr_phi_combo_dnu(op, B, h, p)) <= 1e-7
 
 
-def test_grad_B_dot_product_test_and_closed_form():
-    op = _adr(24, 20, nu=0.02)
+@pytest.mark.parametrize("tr", [False, True])
+def test_grad_B_dot_product_test_and_closed_form(tr):
+    op = dataclasses.replace(_adr(24, 20, nu=0.02), transpose=tr)
     rng = np.random.default_rng(9)
     g = rng.standard_normal(op.n)
     h, p = 0.05, 2
@@ -113,3 +114,23 @@ def test_grad_B_dot_product_test_and_closed_form():
         Bk[:, k] = v
         yk = closed_form.adr_phi_combo(op, Bk, h, k)
         assert abs(g @ yk - Gc[:, k] @ v) <= 1e-11 * abs(g) @ abs(yk)
+
+
+@pytest.mark.parametrize("coef", ["nu", "ax", "ay", "react"])
+def test_closed_form_coefficient_derivatives_equal_central_differences(coef):
+    op = _adr(32, 24, nu=0.02, ax=1.0, ay=-0.5, react=0.3)
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((op.n, 4))
+    h, p, eps = 0.05, 3, 1e-6
+    unit = {"nu": 0.0, "ax": 0.0, "ay": 0.0, "react": 0.0}
+    unit[coef] = 1.0
+    d = closed_form.adr_phi_combo_deriv(op, _dir(op, **unit), B, h, p)
+    v = getattr(op, coef)
+    yp = closed_form.adr_phi_combo(dataclasses.replace(op, **{coef: v + eps}), B, h, p)
+    ym = closed_form.adr_phi_combo(dataclasses.replace(op, **{coef: v - eps}), B, h, p)
+    assert _rel(d, (yp - ym) / (2 * eps)) <= 1e-6
+    for tr in (False, True):             # and the tangent Krylov solve, both orientations
+        opt = dataclasses.replace(op, transpose=tr)
+        _, dy, _ = adjoint.phi_combo_tangent(opt, _dir(opt, **unit), B, h, p, tol=1e-11,
+                                             m_max=48, orth="hybrid")
+        assert _rel(dy, closed_form.adr_phi_combo_deriv(opt, _dir(opt, **unit), B, h, p)) <= 1e-8
