@@ -1100,7 +1100,8 @@ int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t 
   if (rc) return rc;
   const int64_t N = a.N;
   if (grad_B && ldgb < N) return KP_EINVAL;
-  if (coef_mask && A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) return KP_EUNSUPPORTED;
+  if (coef_mask && ((A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) || 2 * p > KP_PMAX))
+    return KP_EUNSUPPORTED;   // refused before any work is enqueued
   if ((rc = device_setup(ctx))) return rc;
   // aux: W = [0_1 .. 0_p | g] (N x (p+1)), then y, dy (N each), dot partials
   const size_t need = sizeof(double) * ((size_t)(p + 3) * N + kp::kDotBlocks);

@@ -314,6 +314,12 @@ def test_backward_entry_brusselator_grad_B_and_rejections():
             ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, coefs=("nu",))
         with pytest.raises(RuntimeError, match=r"\[-1\]"):   # nothing asked for
             ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, want_B=False, coefs=())
+    pr5 = W.random_problem(55, nx=24, ny=20, p=5)
+    with kp.Context() as ctx:
+        with pytest.raises(RuntimeError, match=r"\[-4\]"):   # 2p > KP_PMAX for the tangent
+            ctx.phi_combo_backward(kp.Operator.from_host(pr5.op), dev_B(pr5.B), pr5.h,
+                                   torch.zeros(pr5.op.n, dtype=torch.float64, device="cuda"),
+                                   coefs=("nu",))
     gB_ref = adjoint.grad_B(pr.op, gh, pr.h, 2, krylov.phi_combo, tol=1e-12, m_max=48,
                             orth="hybrid")
     assert rel(gB.cpu().numpy().T, gB_ref) <= 1e-9
