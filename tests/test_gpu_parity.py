@@ -357,3 +357,27 @@ def test_full_size_config2_fixed_substep():
     say(f"  rel={rel(y, ref):.3e} err_est gpu={info['err_max']:.3e} oracle={rinfo.err_max:.3e}")
     assert info["arnoldi_steps"] == 64
     assert rel(y, ref) <= FP64_TOL
+
+
+def test_full_size_fp32_basis_brusselator():
+    """The FP32-basis workload at full size (2 x 2048^2 Brusselator Jacobian,
+    N = 8,388,608, p = 2, h = 0.01, tol 1e-6, m <= 64): the FP32-basis result
+    against the FP64 path (the task's 1e-5), and the FP64 path on a short fixed
+    schedule against the oracle element by element (every workgroup streams
+    several sub-tiles per plane at this size)."""
+    pr = W.config3()
+    say("full-size cfg3: GPU")
+    op, B = dev(pr)
+    with kp.Context(basis="f32") as ctx:
+        y32, i32 = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=pr.m_max, info=True)
+    with kp.Context() as ctx:
+        y64, i64 = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=pr.m_max, info=True)
+    with kp.Context(fixed_m=8, fixed_substeps=1) as ctx:
+        yf = ctx.phi_combo(op, B, pr.h, m_max=8).cpu().numpy()
+    e = rel(y32.cpu().numpy(), y64.cpu().numpy())
+    say(f"  f32 vs f64 rel {e:.2e} (substeps f32 {i32['substeps']} f64 {i64['substeps']})")
+    assert i32["status"] == 0 and i64["status"] == 0 and e <= FP32_TOL
+    say("full-size cfg3: oracle, fixed m = 8")
+    ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=8, fixed_substeps=1, m_max=8)
+    say(f"  fixed m=8 rel {rel(yf, ref):.2e}")
+    assert rel(yf, ref) <= FP64_TOL
