@@ -343,3 +343,15 @@ def test_autograd_advection_and_reaction_coefficients():
                                                          h, p))
         say(f"  autograd d/d{name}: {float(t[name].grad):.12e} ref {ref:.12e}")
         assert abs(float(t[name].grad) - ref) <= 1e-8 * abs(ref)
+
+
+def test_tangent_wide_grid():
+    """Tangent mode doubles the planes: 2 * 2 * nx > 8192 already at nx = 2100,
+    so both planes' halo rows are read with coherent loads."""
+    pr = W.random_problem(62, kind=W.OP_ADR, nx=2100, ny=9, p=2, h=0.02, with_diag=True)
+    op = kp.Operator.from_host(pr.op)
+    with kp.Context(fixed_m=24, fixed_substeps=2) as ctx:
+        y, dy = ctx.phi_combo_tangent(op, dev_dir(op, *DIRECTION), dev_B(pr.B), pr.h, m_max=24)
+    ry, rdy, _ = adjoint.phi_combo_tangent(pr.op, host_dir(pr.op, *DIRECTION), pr.B, pr.h, 2,
+                                           fixed_m=24, fixed_substeps=2, m_max=24)
+    assert rel(y.cpu().numpy(), ry) <= FP64_TOL and rel(dy.cpu().numpy(), rdy) <= FP64_TOL

@@ -381,3 +381,19 @@ def test_full_size_fp32_basis_brusselator():
     ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=8, fixed_substeps=1, m_max=8)
     say(f"  fixed m=8 rel {rel(yf, ref):.2e}")
     assert rel(yf, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("case", [(W.OP_ADR, 4101, 6, 2), (W.OP_ALLEN_CAHN, 4200, 5, 1),
+                                  (W.OP_BRUSSELATOR, 2051, 4, 2)])
+def test_wide_grids_halo_rows_through_coherent_loads(case):
+    """Grids whose two halo rows per plane do not fit the matvec's LDS copy
+    (2 * planes * nx > 8192): the stencil reads them with coherent loads."""
+    kind, nx, ny, p = case
+    say(f"wide kind={kind} {nx}x{ny}")
+    pr = W.random_problem(61, kind=kind, nx=nx, ny=ny, p=p, h=0.02, with_diag=True)
+    op, B = dev(pr)
+    with kp.Context(fixed_m=24, fixed_substeps=2) as ctx:
+        y, info = ctx.phi_combo(op, B, pr.h, m_max=24, info=True)
+    ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=24, fixed_substeps=2, m_max=24)
+    say(f"  rel {rel(y.cpu().numpy(), ref):.2e}")
+    assert info["status"] == 0 and rel(y.cpu().numpy(), ref) <= FP64_TOL
