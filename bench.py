@@ -265,6 +265,8 @@ def main():
         del B3, o3
 
     # ---- adjoint: loss ||phi_combo - y||^2, gradients in B and nu ------------
+    # (the nu-gradient of this constant-coefficient operator is one plain solve
+    # with p + 2 right-hand sides: the direction commutes with A)
     if not args.no_adjoint:
         from paper_2410_14917_amd import autograd as kpa
         torch.cuda.empty_cache()
@@ -313,9 +315,13 @@ def main():
             _, inf = c5.phi_combo(opt5, Bk, p5.h, tol=p5.tol, m_max=p5.m_max, info=True)
             solves[f"transposed_k{k}"] = (timed(lambda: c5.phi_combo(
                 opt5, Bk, p5.h, tol=p5.tol, m_max=p5.m_max)), inf)
+        _, _, inf = c5.phi_combo_backward(op5, Bd, p5.h, g5, tol=p5.tol, m_max=p5.m_max,
+                                          want_B=False, coefs=("nu",), info=True)
+        solves["nu_gradient"] = (timed(lambda: c5.phi_combo_backward(
+            op5, Bd, p5.h, g5, tol=p5.tol, m_max=p5.m_max, want_B=False, coefs=("nu",))), inf)
         _, _, inf = c5.phi_combo_tangent(op5, dop5, Bd, p5.h, tol=p5.tol, m_max=p5.m_max,
                                          info=True)
-        solves["tangent"] = (timed(lambda: c5.phi_combo_tangent(
+        solves["tangent_for_reference"] = (timed(lambda: c5.phi_combo_tangent(
             op5, dop5, Bd, p5.h, tol=p5.tol, m_max=p5.m_max)), inf)
         c5.close()
         kpa.release_contexts()

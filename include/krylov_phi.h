@@ -191,21 +191,26 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
  *                   functions of A^T are the transposes of those of A);
  *                   p + 1 solves as in kp_phi_combo.
  *   grad_coef[c]  = <g, dy/dtheta_c> for every bit c of coef_mask, theta =
- *                   (nu, ax, ay, react) (bits 0..3): one kp_phi_combo_tangent
- *                   solve with the unit direction of that coefficient
- *                   (dA = Lap, -Dx, -Dy or I; transposed with A), then a
- *                   fixed-order device inner product.
+ *                   (nu, ax, ay, react) (bits 0..3), with the unit direction
+ *                   L of that coefficient (Lap, -Dx, -Dy or I; transposed
+ *                   with A), then a fixed-order device inner product.  For a
+ *                   constant-coefficient ADR operator (no field) L and A
+ *                   commute (both circulant) and dy/dtheta is one phi
+ *                   combination of A with the p+2 right-hand sides
+ *                   c_j = h L b_j - (j-1) L b_{j-1} (from phi_k' = phi_k -
+ *                   k phi_{k+1}); otherwise one kp_phi_combo_tangent solve.
  *   g       : device, N doubles.
  *   grad_B  : device, N x (p+1) column-major with leading dimension
  *             ldgb >= N, or NULL (no B-gradient); disjoint from B and g.
  *   grad_coef: device, 4 doubles (entries of unset bits untouched), NULL
  *             only when coef_mask = 0.
- *   Coefficient gradients need KP_OP_ADR or KP_OP_ALLEN_CAHN and 2p <= KP_PMAX.
+ *   Coefficient gradients need KP_OP_ADR or KP_OP_ALLEN_CAHN, and p + 1 <=
+ *   KP_PMAX (constant-coefficient ADR) or 2p <= KP_PMAX (otherwise).
  *   info    : optional; when non-NULL every solve is synchronised and info
  *             gets the worst status and the summed work of all the solves.
  * Asynchronous unless info is requested; no tape of the forward call is
  * needed (the solves recompute what they need).  The context keeps a
- * workspace of (p + 3) N doubles for it.
+ * workspace of at most (2p + 5) N doubles for it.
  * Errors: KP_EINVAL, KP_EUNSUPPORTED, KP_ENOMEM, KP_EHIP.
  */
 int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,

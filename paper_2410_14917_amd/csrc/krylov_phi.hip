@@ -360,6 +360,42 @@ __global__ __launch_bounds__(64) void k_batch_info(BatchDesc d, kp_info* out) {
   out[i] = r;
 }
 
+// Right-hand sides of the derivative of the phi combination along a
+// constant-coefficient stencil direction L that commutes with A (periodic
+// constant-coefficient ADR: both are circulant):
+//   d/dtheta sum_k h^k phi_k(hA) b_k = sum_{j=0}^{p+1} h^j phi_j(hA) c_j,
+//   c_j = h L b_j - (j - 1) L b_{j-1}   (b_{p+1} = b_{-1} = 0),
+// from d/dtheta phi_k(hA) = h L phi_k'(hA) and phi_k' = phi_k - k phi_{k+1}.
+// L = lc (Lap) - la.(Dx, Dy) (sign flipped when transposed) + lr I on the
+// nx x ny periodic grid.  One thread per grid point and column; C is
+// N x (p+2) with leading dimension N.
+__global__ __launch_bounds__(256) void k_dir_rhs(const double* B, int64_t ldb, int p, int nx,
+                                                 int ny, double cx, double cy, double adx,
+                                                 double ady, double lr, int transpose, double h,
+                                                 double* C) {
+  const int64_t npt = (int64_t)nx * ny;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npt * (p + 2)) return;
+  const int j = (int)(t / npt);
+  const int64_t e = t - (int64_t)j * npt;
+  const int row = (int)(e / nx), ix = (int)(e - (int64_t)row * nx);
+  const int64_t ie = row * (int64_t)nx + (ix + 1 == nx ? 0 : ix + 1);
+  const int64_t iw = row * (int64_t)nx + (ix == 0 ? nx - 1 : ix - 1);
+  const int64_t in = (row + 1 == ny ? 0 : row + 1) * (int64_t)nx + ix;
+  const int64_t is = (row == 0 ? ny - 1 : row - 1) * (int64_t)nx + ix;
+  auto Lb = [&](int k) {
+    const double* b = B + (int64_t)k * ldb;
+    const double c = b[e];
+    const double adv = adx * (b[ie] - b[iw]) + ady * (b[in] - b[is]);
+    return cx * (b[ie] + b[iw] - 2.0 * c) + cy * (b[in] + b[is] - 2.0 * c) +
+           (transpose ? adv : -adv) + lr * c;
+  };
+  double v = 0.0;
+  if (j <= p) v += h * Lb(j);
+  if (j >= 1) v -= (double)(j - 1) * Lb(j - 1);
+  C[t] = v;
+}
+
 // <x, y> in a fixed order (the gradient of the loss in an operator
 // coefficient): 256 workgroups each reduce one contiguous chunk, then one
 // workgroup sums the 256 partials.
@@ -1100,16 +1136,24 @@ int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t 
   if (rc) return rc;
   const int64_t N = a.N;
   if (grad_B && ldgb < N) return KP_EINVAL;
-  if (coef_mask && ((A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) || 2 * p > KP_PMAX))
+  if (coef_mask && ((A->kind != KP_OP_ADR && A->kind != KP_OP_ALLEN_CAHN) ||
+                    (A->kind == KP_OP_ADR && !A->field0 ? p + 1 : 2 * p) > KP_PMAX))
     return KP_EUNSUPPORTED;   // refused before any work is enqueued
   if ((rc = device_setup(ctx))) return rc;
-  // aux: W = [0_1 .. 0_p | g] (N x (p+1)), then y, dy (N each), dot partials
-  const size_t need = sizeof(double) * ((size_t)(p + 3) * N + kp::kDotBlocks);
+  // Coefficient directions commute with a constant-coefficient ADR operator
+  // (all are circulant): the derivative is then one plain solve with the
+  // p + 2 right-hand sides of k_dir_rhs; otherwise a tangent solve.
+  const bool commuting = A->kind == KP_OP_ADR && !A->field0;
+  // aux: W = [0_1 .. 0_p | g] (N x (p+1)), then y, dy (N each), dot partials,
+  // then C (N x (p+2)) for the commuting directions
+  const size_t need =
+      sizeof(double) * ((size_t)(p + 3) * N + kp::kDotBlocks + (commuting ? (size_t)(p + 2) * N : 0));
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->aux), &ctx->aux_bytes, need))) return rc;
   double* W = ctx->aux;
   double* y = W + (size_t)(p + 1) * N;
   double* dy = y + N;
   double* part = dy + N;
+  double* C = part + kp::kDotBlocks;
   if (grad_B && (overlaps(grad_B, (size_t)ldgb * (p + 1) * sizeof(double), g, N * sizeof(double)) ||
                  overlaps(grad_B, (size_t)ldgb * (p + 1) * sizeof(double), B,
                           (size_t)ldb * (p + 1) * sizeof(double))))
@@ -1153,7 +1197,17 @@ int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t 
     dA.ax = c == 1 ? 1.0 : 0.0;
     dA.ay = c == 2 ? 1.0 : 0.0;
     dA.react = c == 3 ? 1.0 : 0.0;
-    if ((rc = kp_phi_combo_tangent(ctx, A, &dA, B, p, ldb, h, tol, m_max, y, dy, ip))) return rc;
+    if (commuting) {
+      const int64_t tot = N * (p + 2);
+      hipLaunchKernelGGL(kp::k_dir_rhs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                         ctx->stream, B, ldb, p, A->nx, A->ny, dA.nu / (A->dx * A->dx),
+                         dA.nu / (A->dy * A->dy), dA.ax / (2.0 * A->dx), dA.ay / (2.0 * A->dy),
+                         dA.react, A->transpose ? 1 : 0, h, C);
+      KP_HIP(ctx, hipGetLastError());
+      if ((rc = kp_phi_combo(ctx, A, C, p + 1, N, h, tol, m_max, dy, ip))) return rc;
+    } else if ((rc = kp_phi_combo_tangent(ctx, A, &dA, B, p, ldb, h, tol, m_max, y, dy, ip))) {
+      return rc;
+    }
     if (info) track(ip);
     hipLaunchKernelGGL(kp::k_dot_partial, dim3(kp::kDotBlocks), dim3(256), 0, ctx->stream, g, dy,
                        N, part);

@@ -314,7 +314,7 @@ def test_backward_entry_brusselator_grad_B_and_rejections():
             ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, coefs=("nu",))
         with pytest.raises(RuntimeError, match=r"\[-1\]"):   # nothing asked for
             ctx.phi_combo_backward(op, dev_B(pr.B), pr.h, g, want_B=False, coefs=())
-    pr5 = W.random_problem(55, nx=24, ny=20, p=5)
+    pr5 = W.random_problem(55, nx=24, ny=20, p=5, with_diag=True)
     with kp.Context() as ctx:
         with pytest.raises(RuntimeError, match=r"\[-4\]"):   # 2p > KP_PMAX for the tangent
             ctx.phi_combo_backward(kp.Operator.from_host(pr5.op), dev_B(pr5.B), pr5.h,
@@ -355,3 +355,39 @@ def test_tangent_wide_grid():
     ry, rdy, _ = adjoint.phi_combo_tangent(pr.op, host_dir(pr.op, *DIRECTION), pr.B, pr.h, 2,
                                            fixed_m=24, fixed_substeps=2, m_max=24)
     assert rel(y.cpu().numpy(), ry) <= FP64_TOL and rel(dy.cpu().numpy(), rdy) <= FP64_TOL
+
+
+def test_backward_commuting_directions_match_tangent_solves():
+    """Constant-coefficient ADR: the coefficient gradients come from one plain
+    solve with the right-hand sides c_j = h L b_j - (j-1) L b_{j-1}; they must
+    equal <g, dy> from the tangent solve (both orientations), and hold at
+    p = 5 (where the tangent solve's doubled tail would not fit) against the
+    closed form."""
+    rng = np.random.default_rng(56)
+    for tr in (False, True):
+        op_h = W.Operator(kind=W.OP_ADR, nx=56, ny=44, nu=0.03, ax=-0.7, ay=0.4, react=0.5,
+                          transpose=tr)
+        Bh = rng.standard_normal((op_h.n, 3))
+        gh = rng.standard_normal(op_h.n)
+        op = kp.Operator.from_host(op_h)
+        g = torch.as_tensor(gh, device="cuda")
+        with kp.Context() as ctx:
+            _, gc = ctx.phi_combo_backward(op, dev_B(Bh), 0.05, g, tol=1e-12, m_max=48,
+                                           want_B=False, coefs=tuple(UNITS))
+            for c, name in enumerate(UNITS):
+                _, dy = ctx.phi_combo_tangent(op, dev_dir(op, *UNITS[name]), dev_B(Bh), 0.05,
+                                              tol=1e-12, m_max=48)
+                ref = float(torch.dot(g, dy))
+                say(f"  T={tr} d/d{name}: commuting {float(gc[c]):.12e} tangent {ref:.12e}")
+                assert abs(float(gc[c]) - ref) <= 1e-8 * abs(ref)
+    op_h = W.Operator(kind=W.OP_ADR, nx=40, ny=36, nu=0.02, ax=1.0, ay=0.5, react=-0.4)
+    Bh = rng.standard_normal((op_h.n, 6))
+    gh = rng.standard_normal(op_h.n)
+    with kp.Context() as ctx:
+        _, gc = ctx.phi_combo_backward(kp.Operator.from_host(op_h), dev_B(Bh), 0.05,
+                                       torch.as_tensor(gh, device="cuda"), tol=1e-12, m_max=48,
+                                       want_B=False, coefs=("nu", "react"))
+    for c, name in ((0, "nu"), (3, "react")):
+        ref = float(gh @ closed_form.adr_phi_combo_deriv(op_h, host_dir(op_h, *UNITS[name]), Bh,
+                                                         0.05, 5))
+        assert abs(float(gc[c]) - ref) <= 1e-8 * abs(ref)
