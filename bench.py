@@ -407,7 +407,7 @@ def main():
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
         except Exception:
             cores = 1
-        reps = 2
+        reps = 5   # ~10-15 s of oracle work on the host cores
         t0 = time.perf_counter()
         for _ in range(reps):
             ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=64, fixed_substeps=1,
