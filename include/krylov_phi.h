@@ -99,7 +99,8 @@ typedef struct kp_config {
     void*   stream;          /* hipStream_t; NULL = the null stream            */
     int32_t orth;            /* KP_ORTH_*, default KP_ORTH_H_GSMGS            */
     int32_t basis_dtype;     /* KP_BASIS_*, default KP_BASIS_F64              */
-    int32_t reserved0;       /* must be 0                                     */
+    int32_t m_init;          /* first Krylov dimension of the adaptive controller;
+                                0 -> min(16, m_max)                             */
     int32_t max_substeps;    /* 0 -> 2000                                     */
     int32_t fixed_m;         /* >0: every substep uses exactly this m          */
     int32_t fixed_substeps;  /* with fixed_m: number of equal substeps (>=1)   */
@@ -108,6 +109,8 @@ typedef struct kp_config {
                                 negative -> 0 (the printed rule)              */
     double  breakdown_eps;   /* lucky breakdown when ||v|| <= eps ||A v_j||;
                                 0 -> 1e-12                                     */
+    double  tau_init;        /* first substep length of the adaptive controller;
+                                0 -> h (clipped to h)                           */
 } kp_config;
 
 /* Outcome of a call (filled after the stream is synchronised). */

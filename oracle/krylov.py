@@ -20,7 +20,7 @@ fixed     fixed_m > 0, fixed_substeps = n: n equal substeps tau = h/n with
 adaptive  the substep controller below.  The paper delegates it to KIOPS and
           does not print its formulas, so this controller is this project's
           own (stated identically in the HIP library):
-            start tau = h, m = min(16, m_max);
+            start tau = h, m = min(16, m_max) (or the given m_init, tau_init);
             omega = err * h / (tol * beta * tau)        (beta = ||w_i||);
             accept iff omega <= 1;
             on reject: if m < m_max, double m (capped) and continue the same
@@ -118,7 +118,8 @@ def _basis(arn, m):
 def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
           fixed_m: int = 0, fixed_substeps: int = 0, orth: str = "mgs",
           tform: str = "gsmgs", max_substeps: int = 2000, delta: float = 1e-10,
-          eps_bd: float = 1e-12, want_orth_loss=False):
+          eps_bd: float = 1e-12, want_orth_loss=False, m_init: int = 16,
+          tau_init: float = 0.0):
     """exp(h M) w for the operator M given by apply(x) = M x, by substepped
     Krylov projections with the schedules above.  Returns (vector, Info)."""
     n = len(w)
@@ -129,8 +130,8 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
         m = fixed_m
         tau = h / nsub
     else:
-        m = min(16, m_max)
-        tau = h
+        m = min(m_init, m_max)
+        tau = min(tau_init, h) if tau_init > 0.0 else h
     t = 0.0
     while t < h:
         if info.substeps >= (nsub if fixed else max_substeps):
@@ -212,7 +213,7 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
               m_max: int = 64, fixed_m: int = 0, fixed_substeps: int = 0,
               orth: str = "mgs", tform: str = "gsmgs", max_substeps: int = 2000,
               delta: float = 1e-10, eps_bd: float = 1e-12, want_orth_loss=False,
-              mu: float = None):
+              mu: float = None, m_init: int = 16, tau_init: float = 0.0):
     """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4)."""
     n = op.n
     B = np.asarray(B, dtype=np.float64)
@@ -232,5 +233,5 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
     r, info = expmv(apply, w, h, tol=tol, m_max=m_max, fixed_m=fixed_m,
                     fixed_substeps=fixed_substeps, orth=orth, tform=tform,
                     max_substeps=max_substeps, delta=delta, eps_bd=eps_bd,
-                    want_orth_loss=want_orth_loss)
+                    want_orth_loss=want_orth_loss, m_init=m_init, tau_init=tau_init)
     return r[:n].copy(), info

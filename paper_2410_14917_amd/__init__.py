@@ -76,12 +76,14 @@ class Context:
     """Owns a kp_ctx (device workspace, configuration, stream)."""
 
     def __init__(self, orth="h-gsmgs", basis="f64", max_substeps=0, fixed_m=0,
-                 fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0, stream=None):
+                 fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0, m_init=0,
+                 tau_init=0.0, stream=None):
         self.lib = _lib.load()
         self._stream = stream
         self.cfg = KpConfig(_stream_handle(stream), _lib.ORTH[orth], _lib.BASIS[basis],
-                            0, int(max_substeps), int(fixed_m),
-                            int(fixed_substeps), float(fallback_delta), float(breakdown_eps))
+                            int(m_init), int(max_substeps), int(fixed_m),
+                            int(fixed_substeps), float(fallback_delta), float(breakdown_eps),
+                            float(tau_init))
         h = ctypes.c_void_p()
         _lib.check(self.lib.kp_create(ctypes.byref(h), ctypes.byref(self.cfg)))
         self.h = h

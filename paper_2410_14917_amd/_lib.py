@@ -41,10 +41,10 @@ class KpOp(ctypes.Structure):
 
 class KpConfig(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("orth", ctypes.c_int32),
-                ("basis_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("basis_dtype", ctypes.c_int32), ("m_init", ctypes.c_int32),
                 ("max_substeps", ctypes.c_int32), ("fixed_m", ctypes.c_int32),
                 ("fixed_substeps", ctypes.c_int32), ("fallback_delta", ctypes.c_double),
-                ("breakdown_eps", ctypes.c_double)]
+                ("breakdown_eps", ctypes.c_double), ("tau_init", ctypes.c_double)]
 
 
 class KpInfo(ctypes.Structure):

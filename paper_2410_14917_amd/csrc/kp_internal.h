@@ -131,6 +131,8 @@ struct Args {
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
   double dcx, dcy, dadx, dady, dreact;   // tangent mode: the direction dA
   int orth, fixed_m, fixed_substeps, max_substeps, m_max;
+  int m0;             // Krylov dimension of the first substep
+  double tau0;        // length of the first substep
   int stop_j;         // pause when this many steps are completed (INT_MAX: never)
   int basis_f32;
   int halo_lds;       // the stencil halo rows fit the LDS copy of the matvec

@@ -189,7 +189,7 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   st->n_fallback = st->breakdowns = st->nlog = st->zero = 0;
   st->m_last = 0;
   st->t = 0.0;
-  st->tau = (a.fixed_m > 0) ? a.h / (double)a.fixed_substeps : a.h;
+  st->tau = a.tau0;
   st->beta = 0.0;
   st->mu = 1.0;
   st->err_max = st->omega = st->err = st->last_nrm2 = 0.0;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchDesc d) {
   int nflags = 0;
   for (int c = 0; c < d.nclass; ++c)
     nflags = max(nflags, batch_args(d.args, c * d.nprob + i).nwg * kFlagStride);
-  init_problem(a, a.fixed_m > 0 ? a.fixed_m : min(16, a.m_max), nflags);
+  init_problem(a, a.m0, nflags);
   if (i == 0) {
     for (int c = kp_tid(); c < d.nclass; c += blockDim.x)
       d.queue[c] = (unsigned long long)(d.class_first[c + 1] - d.class_first[c]) << 32;
@@ -488,7 +488,8 @@ int hip_fail(kp_ctx* c, hipError_t e, const char* what) {
 int check_config(const kp_config* c) {
   if (c->orth < 0 || c->orth > KP_ORTH_H_NCWY) return KP_EINVAL;
   if (c->basis_dtype != KP_BASIS_F64 && c->basis_dtype != KP_BASIS_F32) return KP_EINVAL;
-  if (c->reserved0 != 0) return KP_EINVAL;
+  if (c->m_init < 0 || c->m_init > KP_MMAX) return KP_EINVAL;
+  if (!std::isfinite(c->tau_init) || c->tau_init < 0.0) return KP_EINVAL;
   if (c->max_substeps < 0 || c->fixed_m < 0 || c->fixed_m > KP_MMAX) return KP_EINVAL;
   if (c->fixed_m > 0 && c->fixed_substeps < 1) return KP_EINVAL;
   if (c->fixed_substeps < 0) return KP_EINVAL;
@@ -574,6 +575,9 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.fixed_substeps = cfg.fixed_m > 0 ? cfg.fixed_substeps : 0;
   r.max_substeps = cfg.max_substeps > 0 ? cfg.max_substeps : 2000;
   r.m_max = m_max;
+  r.m0 = cfg.fixed_m > 0 ? cfg.fixed_m : std::min(cfg.m_init > 0 ? cfg.m_init : 16, m_max);
+  r.tau0 = cfg.fixed_m > 0 ? h / (double)std::max(1, cfg.fixed_substeps)
+                           : (cfg.tau_init > 0.0 ? std::min(cfg.tau_init, h) : h);
   r.stop_j = INT_MAX;
   r.basis_f32 = cfg.basis_dtype == KP_BASIS_F32 ? 1 : 0;
   r.h = h;
@@ -1013,7 +1017,7 @@ void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ti
 
 extern "C" {
 
-int kp_version(void) { return 10100; }
+int kp_version(void) { return 10200; }
 
 const char* kp_strerror(int code) {
   switch (code) {
@@ -1071,7 +1075,7 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_
   int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, out, true, &a);
   if (rc) return rc;
   if ((rc = prepare(ctx, &a))) return rc;
-  const int m0 = a.fixed_m > 0 ? a.fixed_m : std::min(16, a.m_max);
+  const int m0 = a.m0;
   if ((rc = launch_init(ctx, a, m0))) return rc;
   if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;
@@ -1115,7 +1119,7 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
   a.dady = dA->ay / (2.0 * A->dy);
   a.dreact = dA->react;
   if ((rc = prepare(ctx, &a))) return rc;
-  const int m0 = a.fixed_m > 0 ? a.fixed_m : std::min(16, a.m_max);
+  const int m0 = a.m0;
   if ((rc = launch_init(ctx, a, m0))) return rc;
   if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;

@@ -38,22 +38,44 @@ def test_constants_match_header():
         assert m and int(m.group(1)) == getattr(_lib, name), name
 
 
-def test_struct_layouts_match_header_sizes():
-    assert ctypes.sizeof(_lib.KpOp) == 4 * 4 + 9 * 8 + 2 * 8
-    assert ctypes.sizeof(_lib.KpConfig) == 8 + 6 * 4 + 2 * 8
-    assert ctypes.sizeof(_lib.KpInfo) == 10 * 4 + 3 * 8
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals the C
+    compiler's for the header."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"kp_op": _lib.KpOp, "kp_config": _lib.KpConfig, "kp_info": _lib.KpInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "krylov_phi.h"',
+             "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_version_and_strerror():
     lib = _lib.load()
-    assert lib.kp_version() == 10100
+    assert lib.kp_version() == 10200
     assert lib.kp_strerror(-1) == b"invalid argument"
     assert lib.kp_strerror(12345) == b"unknown error"
 
 
 def _ctx(**kw):
     lib = _lib.load()
-    cfg = _lib.KpConfig(None, 0, 0, 0, 0, 0, 0, 0.0, 0.0)
+    cfg = _lib.KpConfig(None, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0)
     for k, v in kw.items():
         setattr(cfg, k, v)
     h = ctypes.c_void_p()
@@ -61,8 +83,10 @@ def _ctx(**kw):
     return lib, h, rc
 
 
-@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("reserved0", 1),
-                                       ("fixed_m", 65), ("max_substeps", -2)])
+@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("m_init", 65),
+                                       ("m_init", -1), ("tau_init", -1.0),
+                                       ("tau_init", float("inf")), ("fixed_m", 65),
+                                       ("max_substeps", -2)])
 def test_create_rejects_bad_config(field, val):
     lib, h, rc = _ctx(**{field: val})
     assert rc == _lib.KP_EINVAL

@@ -397,3 +397,23 @@ def test_wide_grids_halo_rows_through_coherent_loads(case):
     ref, _ = krylov.phi_combo(pr.op, pr.B, pr.h, p, fixed_m=24, fixed_substeps=2, m_max=24)
     say(f"  rel {rel(y.cpu().numpy(), ref):.2e}")
     assert info["status"] == 0 and rel(y.cpu().numpy(), ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("m_init,tau_init", [(8, 0.0), (32, 0.02), (4, 0.5)])
+def test_controller_start_values(m_init, tau_init):
+    """m_init and tau_init (tau_init > h is clipped to h): the same decisions
+    and result as the oracle with the same start values, single and batched."""
+    pr = W.random_problem(81, kind=W.OP_ADR, nx=72, ny=60, p=2, h=0.1, nu=0.05, react=-0.3)
+    op, B = dev(pr)
+    with kp.Context(m_init=m_init, tau_init=tau_init) as ctx:
+        y, info = ctx.phi_combo(op, B, pr.h, tol=1e-8, m_max=48, info=True)
+        sched = ctx.schedule()
+        (yb,), (ib,) = ctx.phi_combo_batched([op], [B], [pr.h], tol=1e-8, m_max=48, info=True)
+    ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, 2, tol=1e-8, m_max=48, orth="hybrid",
+                                  m_init=m_init, tau_init=tau_init)
+    say(f"  m_init={m_init} tau_init={tau_init}: first {sched[0]} oracle {rinfo.schedule[0]}")
+    assert info["status"] == 0 and ib["status"] == 0
+    assert [s[1] for s in sched] == [s[1] for s in rinfo.schedule]
+    assert np.allclose([s[0] for s in sched], [s[0] for s in rinfo.schedule], rtol=0,
+                       atol=1e-6 * pr.h)
+    assert rel(y.cpu().numpy(), ref) <= FP64_TOL and rel(yb.cpu().numpy(), ref) <= FP64_TOL

@@ -111,3 +111,19 @@ def test_error_estimate_tracks_true_error():
                                    m_max=m)
         err = np.linalg.norm(y - ref)
         assert 0.01 * info.err_max <= err <= 100 * info.err_max
+
+
+@pytest.mark.parametrize("m_init,tau_init", [(4, 0.0), (48, 0.0), (16, 0.01), (8, 0.2)])
+def test_controller_start_values_keep_accuracy(m_init, tau_init):
+    """Any first Krylov dimension and first step reach the closed form within
+    tol (the controller corrects them); tau_init beyond h is clipped to h."""
+    op = W.Operator(kind=W.OP_ADR, nx=48, ny=40, nu=0.05, ax=1.0, ay=0.5, react=-0.3)
+    rng = np.random.default_rng(71)
+    B = rng.standard_normal((op.n, 3))
+    y, info = krylov.phi_combo(op, B, 0.1, 2, tol=1e-9, m_max=48, m_init=m_init,
+                               tau_init=tau_init, orth="hybrid")
+    assert info.status == 0
+    assert np.linalg.norm(y - closed_form.adr_phi_combo(op, B, 0.1, 2)) <= \
+        10 * 1e-9 * np.linalg.norm(y)
+    if tau_init == 0.0 or tau_init >= 0.1:
+        assert info.schedule[0][0] <= 0.1
