@@ -417,3 +417,21 @@ def test_controller_start_values(m_init, tau_init):
     assert np.allclose([s[0] for s in sched], [s[0] for s in rinfo.schedule], rtol=0,
                        atol=1e-6 * pr.h)
     assert rel(y.cpu().numpy(), ref) <= FP64_TOL and rel(yb.cpu().numpy(), ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("delta,oracle_delta", [(1.0, 1.0), (-1.0, 0.0), (1e-4, 1e-4)])
+def test_norm_estimate_fallback_settings(delta, oracle_delta):
+    """The estimate's fallback threshold: 1.0 takes the exact norm at every
+    step (the exact-norm mode, at no extra pass), a negative value the printed
+    rule (delta = 0); decisions, fallback counts and results as the oracle's."""
+    pr = W.random_problem(91, kind=W.OP_ALLEN_CAHN, nx=64, ny=56, p=2, h=0.05)
+    op, B = dev(pr)
+    with kp.Context(fallback_delta=delta, fixed_m=32, fixed_substeps=2) as ctx:
+        y, info = ctx.phi_combo(op, B, pr.h, m_max=32, info=True)
+    ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, 2, fixed_m=32, fixed_substeps=2, m_max=32,
+                                  orth="hybrid", delta=oracle_delta)
+    say(f"  delta={delta}: n_fallback gpu {info['n_fallback']} oracle {rinfo.n_fallback}")
+    assert info["n_fallback"] == rinfo.n_fallback
+    if delta == 1.0:
+        assert info["n_fallback"] == info["arnoldi_steps"]         # every step
+    assert rel(y.cpu().numpy(), ref) <= FP64_TOL
