@@ -1,4 +1,6 @@
-"""Build libkrylov_phi.so in-tree with hipcc for gfx950."""
+"""Build libkrylov_phi.so in-tree with hipcc for gfx950, and the C-ABI test
+client (tests/c_abi_client: host C++ against the HIP runtime and the library,
+no Python)."""
 from __future__ import annotations
 
 import os
@@ -8,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "krylov_phi.hip")
 OUT = os.path.join(HERE, "libkrylov_phi.so")
+CLIENT_SRC = os.path.join(ROOT, "tests", "c_abi_client.cpp")
+CLIENT = os.path.join(ROOT, "tests", "c_abi_client")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -24,7 +29,26 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, OUT)
+    build_client(verbose)
     return OUT
+
+
+def build_client(verbose: bool = False) -> str:
+    """Host-only program: g++ with the HIP runtime headers; it finds the
+    library next to it in the tree through an $ORIGIN-relative rpath."""
+    cxx = os.environ.get("CXX", "g++")
+    tmp = CLIENT + ".tmp"
+    cmd = [cxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+           "-I" + os.path.join(ROCM, "include"), CLIENT_SRC, "-o", tmp, "-L" + HERE,
+           "-lkrylov_phi", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../paper_2410_14917_amd", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("building the C-ABI client failed:\n" + res.stdout + res.stderr)
+    if verbose:
+        print(" ".join(cmd))
+    os.replace(tmp, CLIENT)
+    return CLIENT
 
 
 if __name__ == "__main__":
