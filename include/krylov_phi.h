@@ -27,6 +27,13 @@
  *    the computation (not converged, non-finite data) are reported in
  *    kp_info.status.  No C++ exception crosses this interface.
  *  - A context is not thread-safe; use one context per stream/thread.
+ *  - The solves are cooperative kernel launches.  On the ROCm runtime this
+ *    library is built for, once a process has made such a launch (as
+ *    kp_phi_combo does directly; the batched call's graph node does not), a
+ *    cooperative launch from another process on the same GPU is refused while
+ *    the first process lives: that call returns KP_EHIP, and kp_last_error
+ *    reports "the operation cannot be performed in the present state".  Drive
+ *    one GPU from one process.
  */
 #ifndef KRYLOV_PHI_H
 #define KRYLOV_PHI_H

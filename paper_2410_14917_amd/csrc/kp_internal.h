@@ -36,6 +36,13 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kMMax = KP_MMAX;
 constexpr int kPMax = KP_PMAX;
 constexpr int kKStride = 2 * kMMax + 8;   // partial-sum slots per workgroup
+// The partial-sum area holds three [part_rows][kKStride] buffers: buffer 0 for the
+// phases whose arrivals are counted (stage, close), buffers 1 and 2 for the
+// Arnoldi steps, alternating with the barrier number (see step_part).
+constexpr int kPartBuffers = 3;
+// Marks a step-buffer slot that has not been written since it was consumed:
+// a signalling NaN, which no arithmetic produces (results are quiet NaNs).
+constexpr unsigned long long kPartEmpty = 0xFFF4A5A5A5A5A5A5ull;
 constexpr int kLdh = kMMax + 1;           // leading dimension of H in the state
 constexpr int kLdt = kMMax;               // leading dimension of L, M^{-1}
 constexpr int kLogMax = 8192;             // logged substeps
@@ -113,7 +120,7 @@ struct Args {
   const double* f1;
   double* out;
   double* dout;       // tangent mode: the directional derivative (plane 0)
-  double* part;       // [nwg][kKStride] partial sums        (coherent)
+  double* part;       // [kPartBuffers][part_rows][kKStride] partial sums (coherent)
   unsigned* sync;     // [0] arrivals, [1] releases, [2] abort (coherent)
   State* st;          // the leader only
   Pub* pub;           // coherent
@@ -126,6 +133,7 @@ struct Args {
   int pb;             // number of phi terms beyond b_0 (columns b_1..b_pb of B)
   int tangent;        // 1: Van Loan block operator [[Atilde, dAtilde], [0, Atilde]]
   int nwg, rows_per_wg;   // workgroups that own rows; rows per workgroup
+  int part_rows;      // rows of each partial-sum buffer (>= nwg, the same for every team class)
   int nteam, wg0;     // workgroups meeting at the barriers (>= nwg); first workgroup of the run of such teams
   int kind, transpose;
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
@@ -294,6 +302,23 @@ __device__ inline void bar_arrive(const Args& a) {
   __syncthreads();
   if (kp_tid() == 0)
     __hip_atomic_fetch_add(a.sync + kSyncArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Arrival at an Arnoldi-step barrier: the leader detects the data itself (the
+// partial sums replace kPartEmpty in the step buffer), so nothing waits for
+// this workgroup's stores; the count is kept so that the targets of the
+// counted barriers stay k * nteam.
+__device__ inline void bar_count(const Args& a) {
+  if (kp_tid() == 0)
+    __hip_atomic_fetch_add(a.sync + kSyncArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Step buffer of barrier k ([part_rows][kKStride], rows < nwg used).  A workgroup resets its row of
+// the buffer of barrier k + 1 to kPartEmpty at the start of phase k (the
+// leader consumed that buffer at barrier k - 1, before releasing it), and the
+// reset reaches the coherent level before any of its later stores does.
+__device__ inline double* step_part(const Args& a, unsigned k) {
+  return a.part + (int64_t)(1 + (int)(k & 1u)) * a.part_rows * kKStride;
 }
 
 // Leader: wait for every arrival at barrier k.  *ok (LDS) = false when

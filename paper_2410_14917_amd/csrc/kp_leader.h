@@ -64,6 +64,70 @@ __device__ __attribute__((always_inline)) inline void reduce_partials(const Args
   __syncthreads();
 }
 
+// The same reduction for an Arnoldi step, read from the step buffer buf
+// without a preceding count of arrivals: each thread reloads its kQ slot
+// pairs until none holds kPartEmpty (the second half of a pair past nslot is
+// never written and not checked), so the data are taken in the load that
+// first sees them.  The sums are formed in reduce_partials' order, so the
+// result is the same to the bit.  *ok (LDS, 1 on entry) is cleared when the
+// wait gives up (the abort flag is then raised).
+__device__ __attribute__((always_inline)) inline void gather_step_partials(const Args& a, const double* buf, int nslot,
+                                                            double* dst, double* grp, int* ok) {
+  constexpr int kP = kThreads / kRg;
+  constexpr int kQ = 32;
+  constexpr unsigned kEmptyLo = (unsigned)kPartEmpty, kEmptyHi = (unsigned)(kPartEmpty >> 32);
+  const int g = kp_tid() / kP, l = kp_tid() % kP;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(buf), (short)0, a.nwg * kKStride * (int)sizeof(double), kBufWord3);
+  __syncthreads();   // grp reuses the LDS of the streaming pass's per-wave sums
+  for (int kb = 0; kb < nslot; kb += 2 * kP) {
+    const int k = kb + 2 * l;
+    if (k < nslot) {
+      const bool second = k + 1 < nslot;
+      double sx = 0.0, sy = 0.0;
+      for (int w0 = 0; w0 < a.nwg; w0 += kQ * kRg) {
+        decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0)) v[kQ];
+        int64_t t0 = 0;
+        for (unsigned it = 0;; ++it) {
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            const int w = w0 + g + kRg * q;
+            v[q] = __builtin_amdgcn_raw_buffer_load_b128(
+                rs, (w * kKStride + k) * (int)sizeof(double), 0, kCoherentAux);
+          }
+          bool empty = false;
+#pragma unroll
+          for (int q = 0; q < kQ; ++q)
+            empty |= (v[q][0] == kEmptyLo && v[q][1] == kEmptyHi) ||
+                     (second && v[q][2] == kEmptyLo && v[q][3] == kEmptyHi);
+          if (!empty) break;
+          if (it == 0) t0 = wall_clock64();
+          __builtin_amdgcn_s_sleep(1);
+          if ((it & 15u) == 15u && (aborted(a) || wait_expired(a, t0))) {
+            *ok = 0;
+            break;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          sx += lo_double(v[q][0], v[q][1]);
+          sy += lo_double(v[q][2], v[q][3]);
+        }
+      }
+      grp[g * kKStride + k] = sx;
+      grp[g * kKStride + k + 1] = sy;
+    }
+  }
+  __syncthreads();
+  for (int k = kp_tid(); k < nslot; k += kThreads) {
+    double s = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < kRg; ++gg) s += grp[gg * kKStride + k];
+    dst[k] = s;
+  }
+  __syncthreads();
+}
+
 // ---- stage leader: balance mu, augmented tail, first phase -----------------
 __device__ __attribute__((always_inline)) inline void leader_stage(const Args& a, double* red, Ctl& nx) {
   double m0 = 0.0, m1 = 0.0;

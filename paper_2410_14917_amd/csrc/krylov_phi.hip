@@ -62,6 +62,12 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
   double* hl = lds + kOffHl;
   const bool lead = wg_rank(a) == 0;
   const Ctl c = cur;
+  // this workgroup's row of the step buffer of barrier k + 1 is free again
+  // (consumed at barrier k - 1): mark it unwritten before anything of this
+  // phase is stored
+  if (wg_rank(a) < a.nwg && kp_tid() < kKStride)
+    cstore(step_part(a, k + 1) + (int64_t)wg_rank(a) * kKStride + kp_tid(),
+           __builtin_bit_cast(double, kPartEmpty));
   // streaming part of the phase (every workgroup that owns rows; the others
   // of a team larger than the row count only meet the barriers)
   if (wg_rank(a) < a.nwg) switch (c.phase) {
@@ -71,15 +77,22 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     case PH_STEP:
       // the update that produces x_j (coefficients of the previous scalar
       // step), then the matvec + grouped dots of step j: one grid-wide sync
+      // (flag_publish also completes the reset above before the partial
+      // sums are stored; without an update the wait is explicit)
       if (c.upd) {
         update_pass<TB>(a, c.j - 1, a.pub->coef, red, false);
         flag_publish(a, k);
         flag_wait_neighbours(a, k);
+      } else {
+        wait_all_stores();
       }
-      if (a.halo_lds)
-        matvec_dots_pass<TB, true>(a, c.j, sacc, hl);
-      else
-        matvec_dots_pass<TB, false>(a, c.j, sacc, hl);
+      {
+        double* prow = step_part(a, k) + (int64_t)wg_rank(a) * kKStride;
+        if (a.halo_lds)
+          matvec_dots_pass<TB, true>(a, c.j, sacc, hl, prow);
+        else
+          matvec_dots_pass<TB, false>(a, c.j, sacc, hl, prow);
+      }
       break;
     case PH_CLOSE:
       update_pass<TB>(a, c.j - 1, a.pub->coef, red, true);
@@ -93,21 +106,27 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     default:
       break;
   }
-  bar_arrive(a);
+  if (c.phase == PH_STEP)
+    bar_count(a);
+  else
+    bar_arrive(a);
   if (!lead) {
     bar_wait(a, k, &cur, &ok);
     return;
   }
   // serial part (workgroup 0)
-  bar_gather(a, k, &ok);
-  if (!ok) return;
+  if (c.phase != PH_STEP) {
+    bar_gather(a, k, &ok);
+    if (!ok) return;
+  }
   if (kp_tid() == 0) nxt = c;
   switch (c.phase) {
     case PH_STAGE:
       leader_stage(a, red, nxt);
       break;
     case PH_STEP:
-      reduce_partials(a, 2 * c.j + 3, tv, grp);
+      gather_step_partials(a, step_part(a, k), 2 * c.j + 3, tv, grp, &ok);
+      if (!ok) return;
       scalar_step(a, c.j, tv, L, wk, nxt);
       break;
     case PH_CLOSE:
@@ -171,6 +190,11 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   }
   for (int i = kp_tid(); i < kMMax + 2; i += blockDim.x) a.pub->coef[i] = 0.0;
   for (int i = kp_tid(); i < nflags; i += blockDim.x) a.flags[i] = 0u;
+  {
+    double* sp = step_part(a, 0);   // both step buffers, consecutive
+    const double empty = __builtin_bit_cast(double, kPartEmpty);
+    for (int i = kp_tid(); i < 2 * a.part_rows * kKStride; i += blockDim.x) sp[i] = empty;
+  }
   if (kp_tid() != 0) return;
   for (int i = 0; i < 16; ++i) a.sync[i] = 0u;   // counters, release word (STAGE), abort
   Pub* pb = a.pub;
@@ -644,6 +668,7 @@ void geometry(int ncu_slots, Args* a) {
   a->rows_per_wg = (int)rows;
   a->nwg = (int)((a->ny + rows - 1) / rows);
   a->nteam = a->nwg;
+  a->part_rows = a->nwg;
 }
 
 // Allocate the workspace for a problem and finish Args.
@@ -663,7 +688,7 @@ int prepare(kp_ctx* ctx, Args* a) {
   }
   geometry(ctx->ncu * occ, a);
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->part), &ctx->part_bytes,
-                 (size_t)a->nwg * kp::kKStride * sizeof(double))))
+                 (size_t)kp::kPartBuffers * a->nwg * kp::kKStride * sizeof(double))))
     return rc;
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->hx), &ctx->hx_bytes,
                  (size_t)a->nwg * a->nplanes * 2 * a->nx * sizeof(double))))
@@ -836,7 +861,7 @@ ProbBufs prob_bufs(const Args& a, int nwg_max) {
   ProbBufs r;
   r.v = align256((size_t)a.ld * (a.m_max + 2) * esz);
   r.u = align256((size_t)a.ld * sizeof(double));
-  r.part = align256((size_t)nwg_max * kp::kKStride * sizeof(double));
+  r.part = align256((size_t)kp::kPartBuffers * nwg_max * kp::kKStride * sizeof(double));
   r.hx = align256((size_t)nwg_max * a.nplanes * 2 * a.nx * sizeof(double));
   r.ex = align256(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);
   r.tx = align256(sizeof(double) * kp::kTailPad);
@@ -1005,6 +1030,7 @@ void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ti
     a.sync = b->sync + 16 * (size_t)i;
     a.flags = b->flags + b->flag_off[i];
     a.wait_ticks = wait_ticks;
+    a.part_rows = b->prob_nwg[i];
     for (int c = 0; c < b->nclass; ++c) {
       Args& r = b->hargs[(size_t)c * np + i];
       r = a;

@@ -26,11 +26,14 @@
     }                                                                    \
   } while (0)
 
+static kp_ctx* g_ctx = nullptr;   // for the detail of a failure
+
 #define CHECK_KP(x)                                                      \
   do {                                                                   \
     int r_ = (x);                                                        \
     if (r_ != KP_OK) {                                                   \
-      fprintf(stderr, "%s: %s\n", #x, kp_strerror(r_));                  \
+      fprintf(stderr, "%s: %s (%s)\n", #x, kp_strerror(r_),              \
+              kp_last_error(g_ctx));                                     \
       return 3;                                                          \
     }                                                                    \
   } while (0)
@@ -69,6 +72,7 @@ int main(int argc, char** argv) {
   }
   kp_ctx* ctx = nullptr;
   CHECK_KP(kp_create(&ctx, &cfg));
+  g_ctx = ctx;
   kp_op A = {};
   A.kind = KP_OP_ADR;
   A.nx = nx;

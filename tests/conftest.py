@@ -9,3 +9,14 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
     config.addinivalue_line("markers", "slow: long CPU oracle run")
+
+
+def pytest_collection_modifyitems(session, config, items):
+    """Run the C-ABI client test (a child process that makes cooperative
+    launches) before any test of this process makes one: while a process that
+    has made a cooperative launch is alive, another process's cooperative
+    launch on the same GPU is refused by the runtime."""
+    first = [it for it in items if it.nodeid.split("::")[0].endswith("test_gpu_c_client.py")]
+    if first:
+        rest = [it for it in items if it not in first]
+        items[:] = first + rest
