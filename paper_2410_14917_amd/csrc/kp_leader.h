@@ -181,7 +181,7 @@ struct LeadLds {
   double sigma[kMMax + 8];
   double gamma[kMMax + 8];
   double wn2[kMMax + 8];
-  int fallback_cur, m_target, breakdown, pad_;
+  int fallback_cur, m_target, breakdown, n_fallback, arnoldi_steps, pad_;
 };
 
 __device__ inline void load_tables(const Args& a, LeadLds& L) {
@@ -200,38 +200,39 @@ __device__ inline void load_tables(const Args& a, LeadLds& L) {
     L.fallback_cur = st->fallback_cur;
     L.m_target = st->m_target;
     L.breakdown = st->breakdown;
+    L.n_fallback = st->n_fallback;
+    L.arnoldi_steps = st->arnoldi_steps;
   }
   __syncthreads();
 }
 
-// Work arrays of the scalar step in LDS (doubles).
-constexpr int kWkL = 0, kWkB = 72, kWkY = 144, kWkP = 216, kWkPart = 288;
-constexpr int kWkDoubles = kWkPart + kWaves * 64;
+// Work arrays of the scalar step in LDS (doubles): L row, b, y, p, H column.
+constexpr int kWkL = 0, kWkB = 72, kWkY = 144, kWkP = 216, kWkH = 288;
+constexpr int kWkDoubles = kWkH + 72;
 
-// dst[i] = sum over k in K(i) of T(i, k) * v[k] for rows i <= jj, where the
-// k range is split over the kWaves waves (wave g takes k = g, g + kWaves, ...)
-// and the partial sums meet in LDS.  T(i, k) = tab[k * kTabLd + i] (TR = false)
-// or tab[i * kTabLd + k] (TR = true, the transposed table).  MODE selects
-// K(i): 0 -> k <= i, 1 -> k < i, 2 -> i < k <= jj.
+// Row r = 8 * wave + lane / 8 of a product of a correction-matrix table with
+// v (LDS): sum over k in K(r) of T(r, k) * v[k].  The 8 lanes of the row take
+// k = lane mod 8, 8, 16, ... (loads all in flight, in bounds for every r, k <
+// kMMax) and their sums meet by DPP inside the 8-lane group, so a product
+// needs no workgroup barrier of its own; every lane of the group gets the
+// row's value.  T(r, k) = tab[k * kTabLd + r] (TR = false) or
+// tab[r * kTabLd + k] (TR = true, the transposed table).  MODE selects K(r):
+// 0 -> k <= r, 1 -> k < r, 2 -> r < k <= hi.
 template <int MODE, bool TR>
-__device__ inline double tri_mv(int jj, const double* tab, const double* v, double* part) {
-  const int i = kp_tid() & 63, g = kp_tid() >> 6;
+__device__ inline double row_mv(int hi, const double* tab, const double* v, int r) {
+  const int s = kp_tid() & 7;
   double acc = 0.0;
-  if (i <= jj) {
-    const int klo = (MODE == 2) ? i + 1 : 0;
-    const int khi = (MODE == 0) ? i : (MODE == 1 ? i - 1 : jj);
-    for (int k = g; k <= khi; k += kWaves)
-      if (k >= klo) acc += (TR ? tab[i * kTabLd + k] : tab[k * kTabLd + i]) * v[k];
-  }
-  part[g * 64 + i] = acc;
-  __syncthreads();
-  double s = 0.0;
-  if (kp_tid() < 64) {
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += part[w * 64 + i];
+  for (int t = 0; t < kMMax / 8; ++t) {
+    const int k = s + 8 * t;
+    const double x = (TR ? tab[r * kTabLd + k] : tab[k * kTabLd + r]) * v[k];
+    const bool in = (MODE == 0) ? (k <= r) : (MODE == 1 ? (k < r) : (k > r && k <= hi));
+    if (in) acc += x;
   }
-  __syncthreads();
-  return s;   // meaningful in wave 0
+  acc += dpp_mov<0xB1>(acc);    // quad_perm [1,0,3,2]
+  acc += dpp_mov<0x4E>(acc);    // quad_perm [2,3,0,1]
+  acc += dpp_mov<0x141>(acc);   // row_half_mirror: the 8-lane sum
+  return acc;
 }
 
 // tv: reduced inner products of step jj (slot layout of matvec_dots_pass).
@@ -250,7 +251,7 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
   double* sb = wk + kWkB;
   double* sy = wk + kWkY;
   double* sp = wk + kWkP;
-  double* part = wk + kWkPart;
+  double* sh = wk + kWkH;
   const int i = kp_tid();               // row index in wave 0
   const bool w0 = kp_tid() < 64;
   const double gj = tv[2 * jj], cj = tv[2 * jj + 1], cww = tv[2 * jj + 2];
@@ -300,40 +301,47 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
     sb[i] = b;
   }
   __syncthreads();
+  // rows of the triangular products: 8 per wave, 8 lanes per row
+  const int r = (kp_tid() >> 6) * 8 + ((kp_tid() & 63) >> 3);
+  const bool row_lead = (kp_tid() & 7) == 0;
   // new row of M^{-1} = (I + L)^{-1} by the compact-WY recursion:
-  // (M^{-1})_{j,i} = -sum_{i <= k < j} L_{j,k} (M^{-1})_{k,i}; the row is
-  // appended to the LDS tables together with the new row of L.
-  const double mr = -tri_mv<2, true>(jj - 1, Mi, sl, part);   // k in (i, jj-1] ...
-  // (tri_mv<2> excludes k == i; add the unit-diagonal term L_{j,i} * 1)
-  if (act) {
-    Mi[i * kTabLd + jj] = mr - l;
-    Li[i * kTabLd + jj] = l;
-  }
-  if (i == 0) {
-    Mi[jj * kTabLd + jj] = 1.0;
-    Li[jj * kTabLd + jj] = 0.0;
+  // (M^{-1})_{j,r} = -sum_{r <= k < j} L_{j,k} (M^{-1})_{k,r}; the row is
+  // appended to the LDS tables together with the new row of L (row_mv<2>
+  // excludes k == r: the unit-diagonal term L_{j,r} * 1 is added here)
+  const double mr = -row_mv<2, true>(jj - 1, Mi, sl, r);
+  if (row_lead) {
+    if (r < jj) {
+      Mi[r * kTabLd + jj] = mr - sl[r];
+      Li[r * kTabLd + jj] = sl[r];
+    } else if (r == jj) {
+      Mi[jj * kTabLd + jj] = 1.0;
+      Li[jj * kTabLd + jj] = 0.0;
+    }
   }
   __syncthreads();
-  double Hi = 0.0;
+  double Hr;
   if (a.orth == KP_ORTH_H_NCWY) {
     // T = I - L:  H = b - L b
-    Hi = b - tri_mv<1, false>(jj, Li, sb, part);
+    Hr = sb[r] - row_mv<1, false>(jj, Li, sb, r);
   } else {
     // y = M^{-1} b  (CWY: H = y)
-    const double y = tri_mv<0, false>(jj, Mi, sb, part);
+    const double y = row_mv<0, false>(jj, Mi, sb, r);
     if (a.orth == KP_ORTH_H_CWY) {
-      Hi = y;
+      Hr = y;
     } else {
       // GSMGS: p = b + N y = b - L^T y, then x = M^{-1} p with the explicit
       // inverse kept above (the same x as the forward substitution M x = p)
-      if (w0) sy[i] = y;
+      if (row_lead) sy[r] = y;
       __syncthreads();
-      const double pv = b - tri_mv<2, true>(jj, Li, sy, part);
-      if (w0) sp[i] = pv;
+      const double pv = sb[r] - row_mv<2, true>(jj, Li, sy, r);
+      if (row_lead) sp[r] = pv;
       __syncthreads();
-      Hi = tri_mv<0, false>(jj, Mi, sp, part);
+      Hr = row_mv<0, false>(jj, Mi, sp, r);
     }
   }
+  if (row_lead) sh[r] = Hr;
+  __syncthreads();
+  double Hi = sh[i & 63];
   if (!w0) return;
   if (i > jj) Hi = 0.0;
   const double ss = wave_sum((i <= jj) ? b * b : 0.0);
@@ -364,7 +372,8 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
     if (jj == 0) st->beta = alpha;
     st->fallback_cur = fallback;
     L.fallback_cur = fallback;
-    st->n_fallback += fallback;
+    L.n_fallback += fallback;
+    st->n_fallback = L.n_fallback;
     if (bad) {
       nx.status = (int)KP_STATUS_NONFINITE;
       nx.phase = (int)PH_FINISH;
@@ -372,14 +381,14 @@ __device__ __attribute__((always_inline)) inline void scalar_step(const Args& a,
       st->H[(int64_t)jj * kLdh + jj + 1] = 0.0;
       st->breakdown = 1;
       L.breakdown = 1;
-      st->arnoldi_steps += 1;
+      st->arnoldi_steps = ++L.arnoldi_steps;
       nx.j = jj + 1;
       nx.m_eff = jj + 1;
       nx.upd = 0;
       nx.phase = (int)PH_EXPM;
     } else {
       const int j = jj + 1;
-      st->arnoldi_steps += 1;
+      st->arnoldi_steps = ++L.arnoldi_steps;
       nx.j = j;
       nx.m_eff = j;
       nx.upd = 1;
