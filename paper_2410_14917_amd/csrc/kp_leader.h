@@ -68,11 +68,13 @@ __device__ __attribute__((always_inline)) inline void reduce_partials(const Args
 // without a preceding count of arrivals: each thread reloads its kQ slot
 // pairs until none holds kPartEmpty (the second half of a pair past nslot is
 // never written and not checked), so the data are taken in the load that
-// first sees them.  The sums are formed in reduce_partials' order, so the
-// result is the same to the bit.  *ok (LDS, 1 on entry) is cleared when the
-// wait gives up (the abort flag is then raised).
+// first sees them.  Row 0 (the leader's own sums) comes from the LDS copy
+// own instead of the buffer.  The sums are formed in reduce_partials' order,
+// so the result is the same to the bit.  *ok (LDS, 1 on entry) is cleared
+// when the wait gives up (the abort flag is then raised).
 __device__ __attribute__((always_inline)) inline void gather_step_partials(const Args& a, const double* buf, int nslot,
-                                                            double* dst, double* grp, int* ok) {
+                                                            const double* own, double* dst, double* grp,
+                                                            int* ok) {
   constexpr int kP = kThreads / kRg;
   constexpr int kQ = 32;
   constexpr unsigned kEmptyLo = (unsigned)kPartEmpty, kEmptyHi = (unsigned)(kPartEmpty >> 32);
@@ -94,6 +96,13 @@ __device__ __attribute__((always_inline)) inline void gather_step_partials(const
             const int w = w0 + g + kRg * q;
             v[q] = __builtin_amdgcn_raw_buffer_load_b128(
                 rs, (w * kKStride + k) * (int)sizeof(double), 0, kCoherentAux);
+          }
+          if (w0 == 0 && g == 0) {     // row 0: the leader's own sums
+            const double o0 = own[k], o1 = second ? own[k + 1] : 0.0;
+            v[0][0] = (unsigned)__double_as_longlong(o0);
+            v[0][1] = (unsigned)((unsigned long long)__double_as_longlong(o0) >> 32);
+            v[0][2] = (unsigned)__double_as_longlong(o1);
+            v[0][3] = (unsigned)((unsigned long long)__double_as_longlong(o1) >> 32);
           }
           bool empty = false;
 #pragma unroll

@@ -518,7 +518,8 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
 // inner products of V_{1:j+1}^T [x_j, w] (eq. output_wywnrm):
 //   slot 2i = x_i . x,  slot 2i+1 = x_i . w  (i <= jj),  slot 2jj+2 = w . w.
 // sacc: kWaves * kKStride doubles of LDS; hl: the LDS halo copy (HL); prow:
-// this workgroup's row of the step buffer of the phase's barrier.
+// this workgroup's row of the step buffer of the phase's barrier; own: the
+// leader's LDS copy of its sums (nullptr in the other workgroups).
 //
 // The older columns are visited kCh at a time, software-pipelined: the loads
 // of the next chunk are in flight while the wave reduces the current one.
@@ -561,7 +562,7 @@ __device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, i
 
 template <typename TB, bool HL>
 __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Args& a, int jj, double* sacc, double* hl,
-                                                        double* prow) {
+                                                        double* prow, double* own) {
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
@@ -636,12 +637,17 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   }
   if (wg_rank(a) == 0) tail_matvec_dots<TB>(a, jj, x, V, sacc);
   __syncthreads();
-  // slot k is written by thread k, the thread that reset it (step_part)
+  // slot k is written by thread k, the thread that reset it (step_part); the
+  // leader keeps its own sums in LDS (own), where its reduction reads them,
+  // so that no store of its own is outstanding when it starts polling
   const int nslot = 2 * jj + 3;
   for (int k = kp_tid(); k < nslot; k += kThreads) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += sacc[w * kKStride + k];
-    cstore(prow + k, s);
+    if (own)
+      own[k] = s;
+    else
+      cstore(prow + k, s);
   }
 }
 

@@ -38,13 +38,14 @@ constexpr int kOffWk = 0;
 constexpr int kOffCoef = kWaves * kKStride;
 constexpr int kOffRed = kOffCoef + kMMax + 8;
 constexpr int kOffTv = kOffRed + kWaves;
+constexpr int kOffOwn = kOffTv + kKStride;   // the leader's own step sums
 constexpr int kOffHl = 1536;
 constexpr int kHaloCap = 8192;            // 2 * nplanes * nx doubles at most
 constexpr int kLdsDoubles = (2 * kNmPad * kNmPad > kOffHl + kHaloCap) ? 2 * kNmPad * kNmPad
                                                                       : kOffHl + kHaloCap;
 static_assert(kOffGrp + kRg * kKStride <= kOffCoef, "grp overlaps coef");
 static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
-static_assert(kOffTv + kKStride <= kOffHl, "tv overlaps the halo copy");
+static_assert(kOffOwn + kKStride <= kOffHl, "tv / own overlap the halo copy");
 static_assert(kLdsDoubles >= kNmPad * kGjLd, "the small exponential does not fit the phase buffer");
 
 // One phase of the call for this workgroup.  cur: control of the phase (LDS,
@@ -59,6 +60,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
   double* wk = lds + kOffWk;
   double* red = lds + kOffRed;
   double* tv = lds + kOffTv;
+  double* own = lds + kOffOwn;
   double* hl = lds + kOffHl;
   const bool lead = wg_rank(a) == 0;
   const Ctl c = cur;
@@ -88,10 +90,11 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       }
       {
         double* prow = step_part(a, k) + (int64_t)wg_rank(a) * kKStride;
+        double* mine = lead ? own : nullptr;
         if (a.halo_lds)
-          matvec_dots_pass<TB, true>(a, c.j, sacc, hl, prow);
+          matvec_dots_pass<TB, true>(a, c.j, sacc, hl, prow, mine);
         else
-          matvec_dots_pass<TB, false>(a, c.j, sacc, hl, prow);
+          matvec_dots_pass<TB, false>(a, c.j, sacc, hl, prow, mine);
       }
       break;
     case PH_CLOSE:
@@ -106,10 +109,12 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     default:
       break;
   }
-  if (c.phase == PH_STEP)
-    bar_count(a);
-  else
+  // (the leader counts its arrival at a step barrier after the release, so
+  // that the atomic is not outstanding while it polls)
+  if (c.phase != PH_STEP)
     bar_arrive(a);
+  else if (!lead)
+    bar_count(a);
   if (!lead) {
     bar_wait(a, k, &cur, &ok);
     return;
@@ -125,7 +130,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       leader_stage(a, red, nxt);
       break;
     case PH_STEP:
-      gather_step_partials(a, step_part(a, k), 2 * c.j + 3, tv, grp, &ok);
+      gather_step_partials(a, step_part(a, k), 2 * c.j + 3, own, tv, grp, &ok);
       if (!ok) return;
       scalar_step(a, c.j, tv, L, wk, nxt);
       break;
@@ -146,6 +151,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       break;
   }
   bar_release(a, k, nxt, a.pub);
+  if (c.phase == PH_STEP) bar_count(a);
   if (kp_tid() == 0) cur = nxt;
 }
 
@@ -314,8 +320,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
       int pi = -1;
       if (lead_wg) {
         // own class first; then the light end of the classes of smaller
-        // teams (classes are ordered by decreasing team size): a problem is
-        // never moved to a team slower on it than the one planned for it
+        // teams (classes are ordered by decreasing team size), solved with
+        // its planned row partition (the Args of such a (class, problem)
+        // pair), so its result is the same whichever team takes it
         pi = queue_take(d, c, true);
         for (int cc = c + 1; pi < 0 && cc < d.nclass; ++cc) pi = queue_take(d, cc, false);
         cstore(slot, ((unsigned long long)seq << 32) | (unsigned)(pi + 1));
@@ -802,6 +809,7 @@ struct BatchCache {
   std::vector<int> class_wg0;         // first workgroup of class c's run of teams
   std::vector<size_t> prob_off;       // arena offset of each problem's buffers
   std::vector<int> prob_nwg;          // largest row-owning workgroup count over the classes
+  std::vector<int> prob_class;        // class the plan gave each problem
   std::vector<int64_t> flag_off;      // per problem, in unsigned
   void* arena = nullptr;              // per-problem buffers
   State* st = nullptr;                // [nprob]
@@ -913,6 +921,9 @@ int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp:
     order.insert(order.end(), lists[c].begin(), lists[c].end());
     class_first.push_back((int)order.size());
   }
+  b->prob_class.assign(np, 0);
+  for (int c = 0; c < nc; ++c)
+    for (int i : lists[c]) b->prob_class[i] = c;
   // per-problem buffers, sized for the class that spreads the problem widest
   b->prob_nwg.assign(np, 1);
   for (int i = 0; i < np; ++i)
@@ -1031,10 +1042,21 @@ void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ti
     a.flags = b->flags + b->flag_off[i];
     a.wait_ticks = wait_ticks;
     a.part_rows = b->prob_nwg[i];
+    // a team of a larger class that takes the problem (from the light end of
+    // its planned class's queue) keeps the planned row partition, its extra
+    // workgroups only meeting the barriers: the partial sums, and so the
+    // result, do not depend on which team solves the problem
+    const int pc = b->prob_class[i];
+    Args planned = a;
+    batch_geometry(b->class_size[pc], b->class_wg0[pc], &planned);
     for (int c = 0; c < b->nclass; ++c) {
       Args& r = b->hargs[(size_t)c * np + i];
       r = a;
       batch_geometry(b->class_size[c], b->class_wg0[c], &r);
+      if (b->class_size[c] > b->class_size[pc]) {
+        r.rows_per_wg = planned.rows_per_wg;
+        r.nwg = planned.nwg;
+      }
     }
   }
 }

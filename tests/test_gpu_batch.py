@@ -163,7 +163,10 @@ def test_batched_rejects_overlapping_outputs():
 def test_full_size_uneven_batch_against_closed_form():
     """512 advection-diffusion-reaction problems, sides U{32..512}
     (N 1,024 .. 262,144, sum ~5.0e7), p = 3, h = 0.05, m <= 48, tol 1e-8, in
-    one batched call; every problem against the DFT closed form."""
+    one batched call; every problem against the DFT closed form.  A second
+    call (a graph replay) gives the same bits: free teams take problems of
+    other classes at run time, but a problem keeps its planned row partition
+    whichever team solves it."""
     probs = W.config4()
     say(f"full-size batch: {len(probs)} problems, N total {sum(q.op.n for q in probs)}")
     ops = [kp.Operator.from_host(q.op) for q in probs]
@@ -171,6 +174,12 @@ def test_full_size_uneven_batch_against_closed_form():
     with kp.Context() as ctx:
         ys, infos = ctx.phi_combo_batched(ops, Bs, [q.h for q in probs], tol=1e-8, m_max=48,
                                           info=True)
+        ys = [y.clone() for y in ys]
+        ys2 = ctx.phi_combo_batched(ops, Bs, [q.h for q in probs], tol=1e-8, m_max=48)
+        torch.cuda.synchronize()
+        ndiff = sum(int(not torch.equal(y, y2)) for y, y2 in zip(ys, ys2))
+    say(f"full-size batch: problems differing between two calls: {ndiff}")
+    assert ndiff == 0
     say("full-size batch: closed forms")
     worst, steps = 0.0, 0
     for q, y, inf in zip(probs, ys, infos):
