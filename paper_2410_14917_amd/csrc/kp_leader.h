@@ -221,21 +221,23 @@ constexpr int kWkDoubles = kWkH + 72;
 
 // Row r = 8 * wave + lane / 8 of a product of a correction-matrix table with
 // v (LDS): sum over k in K(r) of T(r, k) * v[k].  The 8 lanes of the row take
-// k = lane mod 8, 8, 16, ... (loads all in flight, in bounds for every r, k <
-// kMMax) and their sums meet by DPP inside the 8-lane group, so a product
-// needs no workgroup barrier of its own; every lane of the group gets the
-// row's value.  T(r, k) = tab[k * kTabLd + r] (TR = false) or
-// tab[r * kTabLd + k] (TR = true, the transposed table).  MODE selects K(r):
-// 0 -> k <= r, 1 -> k < r, 2 -> r < k <= hi.
+// k = lane mod 8, 8, 16, ... up to hi (loads in flight together, in bounds
+// for every r, k < kMMax) and their sums meet by DPP inside the 8-lane group,
+// so a product needs no workgroup barrier of its own; every lane of the group
+// gets the row's value.  T(r, k) = tab[k * kTabLd + r] (TR = false) or
+// tab[r * kTabLd + k] (TR = true, the transposed table).  MODE selects K(r),
+// always within k <= hi (the rows used are r <= hi): 0 -> k <= r, 1 -> k < r,
+// 2 -> r < k.
 template <int MODE, bool TR>
 __device__ inline double row_mv(int hi, const double* tab, const double* v, int r) {
   const int s = kp_tid() & 7;
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < kMMax / 8; ++t) {
+    if (8 * t > hi) break;                     // uniform: no row needs these k
     const int k = s + 8 * t;
     const double x = (TR ? tab[r * kTabLd + k] : tab[k * kTabLd + r]) * v[k];
-    const bool in = (MODE == 0) ? (k <= r) : (MODE == 1 ? (k < r) : (k > r && k <= hi));
+    const bool in = (k <= hi) && ((MODE == 0) ? (k <= r) : (MODE == 1 ? (k < r) : (k > r)));
     if (in) acc += x;
   }
   acc += dpp_mov<0xB1>(acc);    // quad_perm [1,0,3,2]
