@@ -119,11 +119,20 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
           fixed_m: int = 0, fixed_substeps: int = 0, orth: str = "mgs",
           tform: str = "gsmgs", max_substeps: int = 2000, delta: float = 1e-10,
           eps_bd: float = 1e-12, want_orth_loss=False, m_init: int = 16,
-          tau_init: float = 0.0):
+          tau_init: float = 0.0, schedule=None):
     """exp(h M) w for the operator M given by apply(x) = M x, by substepped
-    Krylov projections with the schedules above.  Returns (vector, Info)."""
+    Krylov projections with the schedules above.  Returns (vector, Info).
+
+    schedule: the replay schedule, a list of accepted substeps (tau_i, m_i):
+    each is one Krylov projection of dimension m_i (fewer at a lucky
+    breakdown) advanced by tau_i, in order; tol, m_max and the controller are
+    not used.  This replays a schedule another implementation logged, so the
+    two results can be compared at rounding level (Section 3's substepping,
+    eq. substep)."""
     n = len(w)
     info = Info()
+    if schedule is not None:
+        return _replay(apply, w, schedule, orth, tform, delta, eps_bd, info)
     fixed = fixed_m > 0
     if fixed:
         nsub = max(1, fixed_substeps)
@@ -209,12 +218,40 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
     return w.copy(), info
 
 
+def _replay(apply, w, schedule, orth, tform, delta, eps_bd, info):
+    """The substeps of a given schedule; see expmv."""
+    for tau, m_i in schedule:
+        arn = _make_arnoldi(orth, apply, w, int(m_i), tform, delta, eps_bd)
+        if orth == "mgs" and arn.beta == 0.0:
+            break
+        mb = arn.extend(int(m_i))
+        beta = arn.beta
+        if not beta:
+            break
+        info.arnoldi_steps += mb
+        Hb = hbar(arn.H, mb)
+        if arn.breakdown:
+            Hb[mb, mb - 1] = 0.0
+            info.breakdowns += 1
+        F = expm_taylor(tau * Hb)[:, 0]
+        info.expm_evals += 1
+        info.err_max = max(info.err_max, 0.0 if arn.breakdown else beta * abs(F[mb]))
+        w = beta * (_basis(arn, mb) @ F[:mb])
+        info.schedule.append((tau, mb))
+        info.substeps += 1
+        info.m_last = mb
+        if isinstance(arn, HybridArnoldi):
+            info.n_fallback += arn.n_fallback
+    return w.copy(), info
+
+
 def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
               m_max: int = 64, fixed_m: int = 0, fixed_substeps: int = 0,
               orth: str = "mgs", tform: str = "gsmgs", max_substeps: int = 2000,
               delta: float = 1e-10, eps_bd: float = 1e-12, want_orth_loss=False,
-              mu: float = None, m_init: int = 16, tau_init: float = 0.0):
-    """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4)."""
+              mu: float = None, m_init: int = 16, tau_init: float = 0.0, schedule=None):
+    """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4);
+    schedule: replay the given accepted substeps (see expmv)."""
     n = op.n
     B = np.asarray(B, dtype=np.float64)
     if not np.all(np.isfinite(B[:, :p + 1])):
@@ -233,5 +270,6 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
     r, info = expmv(apply, w, h, tol=tol, m_max=m_max, fixed_m=fixed_m,
                     fixed_substeps=fixed_substeps, orth=orth, tform=tform,
                     max_substeps=max_substeps, delta=delta, eps_bd=eps_bd,
-                    want_orth_loss=want_orth_loss, m_init=m_init, tau_init=tau_init)
+                    want_orth_loss=want_orth_loss, m_init=m_init, tau_init=tau_init,
+                    schedule=schedule)
     return r[:n].copy(), info

@@ -359,6 +359,29 @@ def test_full_size_config2_fixed_substep():
     assert rel(y, ref) <= FP64_TOL
 
 
+def test_full_size_config2_adaptive_against_oracle_replay():
+    """The benchmark's adaptive call (Allen-Cahn 1024^2, tol 1e-8, m <= 64, the
+    launch configuration bench.py times): the oracle's hybrid Arnoldi
+    (H-GSMGS) replaying the GPU's accepted substeps gives the same result
+    element by element.  About a minute of CPU work for the oracle."""
+    pr = W.config2()
+    say("full-size cfg2 adaptive: GPU")
+    op, B = dev(pr)
+    with kp.Context() as ctx:
+        y, info = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=64, info=True)
+        sched = ctx.schedule()
+    y = y.cpu().numpy()
+    say(f"  {info['substeps']} substeps ({info['rejected']} rejected), "
+        f"{info['arnoldi_steps']} Arnoldi steps; oracle replay of {len(sched)} substeps")
+    assert info["status"] == 0 and info["t_end"] == pr.h and len(sched) == info["substeps"]
+    assert abs(sum(t for t, _ in sched) - pr.h) <= 1e-12 * pr.h
+    ref, rinfo = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, orth="hybrid", tform="gsmgs",
+                                  schedule=sched)
+    say(f"  rel err vs oracle replay {rel(y, ref):.3e}")
+    assert rinfo.substeps == len(sched)
+    assert rel(y, ref) <= FP64_TOL
+
+
 def test_full_size_fp32_basis_brusselator():
     """The FP32-basis workload at full size (2 x 2048^2 Brusselator Jacobian,
     N = 8,388,608, p = 2, h = 0.01, tol 1e-6, m <= 64): the FP32-basis result

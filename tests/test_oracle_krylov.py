@@ -127,3 +127,46 @@ def test_controller_start_values_keep_accuracy(m_init, tau_init):
         10 * 1e-9 * np.linalg.norm(y)
     if tau_init == 0.0 or tau_init >= 0.1:
         assert info.schedule[0][0] <= 0.1
+
+
+# ---- replay of a logged schedule -------------------------------------------
+
+def test_replay_of_equal_substeps_is_the_fixed_schedule():
+    """Replaying n substeps of h/n with dimension m is the fixed schedule,
+    to the bit (the same projections in the same order)."""
+    pr = W.random_problem(7, kind=W.OP_ADR, nx=12, ny=10, p=2, h=0.3)
+    for orth in ("mgs", "hybrid"):
+        y_f, _ = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, fixed_m=12, fixed_substeps=3,
+                                  m_max=12, orth=orth)
+        y_r, info = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, orth=orth,
+                                     schedule=[(pr.h / 3, 12)] * 3)
+        assert np.array_equal(y_f, y_r) and info.substeps == 3 and info.arnoldi_steps == 36
+
+
+def test_replay_of_uneven_substeps_matches_closed_form():
+    """Substeps of 0.3 h, 0.5 h and 0.2 h (converged dimension 40) give the
+    DFT closed form of the whole step (Section 3: the substeps compose the
+    exponential of the augmented matrix)."""
+    pr = W.config1()
+    h = pr.h
+    y, info = krylov.phi_combo(pr.op, pr.B, h, pr.p, orth="hybrid",
+                               schedule=[(0.3 * h, 40), (0.5 * h, 40), (0.2 * h, 40)])
+    ref = closed_form.adr_phi_combo(pr.op, pr.B, h, pr.p)
+    assert info.substeps == 3 and rel(y, ref) <= 1e-12
+    # a dropped substep is a different result
+    y2, _ = krylov.phi_combo(pr.op, pr.B, h, pr.p, orth="hybrid",
+                             schedule=[(0.3 * h, 40), (0.5 * h, 40)])
+    assert rel(y2, ref) > 1e-3
+
+
+def test_replay_of_an_adaptive_schedule_reproduces_the_run():
+    """The accepted substeps of an adaptive run (with rejections and growth of
+    m), replayed, give the run's result to rounding."""
+    pr = W.random_problem(11, kind=W.OP_ADR, nx=24, ny=20, p=2, h=0.5)
+    y_a, info_a = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, tol=1e-8, m_max=24,
+                                   orth="hybrid")
+    assert info_a.substeps >= 2
+    y_r, info_r = krylov.phi_combo(pr.op, pr.B, pr.h, pr.p, orth="hybrid",
+                                   schedule=info_a.schedule)
+    assert info_r.schedule == info_a.schedule
+    assert rel(y_r, y_a) <= 1e-13
