@@ -34,6 +34,11 @@
  *    the first process lives: that call returns KP_EHIP, and kp_last_error
  *    reports "the operation cannot be performed in the present state".  Drive
  *    one GPU from one process.
+ *  - The library links the system HIP runtime.  In a process that also uses a
+ *    second copy (PyTorch ships its own), load that copy first: loaded after
+ *    this library, its initialisation leaves this library's first device
+ *    query reporting no device (KP_EHIP from the first call that touches
+ *    the device).
  */
 #ifndef KRYLOV_PHI_H
 #define KRYLOV_PHI_H

@@ -72,6 +72,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         raise RuntimeError(
             f"{path} is missing: build it with paper_2410_14917_amd.build.build() "
             "(there is no CPU fallback)")
+    # The library links the system HIP runtime; PyTorch carries its own copy.
+    # With both in one process, torch's has to be loaded first: loaded the
+    # other way round, the library's first device query reports no device
+    # once torch has initialised its runtime (measured on MI355X, ROCm 7.2).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.kp_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KpConfig)]
