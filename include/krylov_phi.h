@@ -34,6 +34,10 @@
  *    the first process lives: that call returns KP_EHIP, and kp_last_error
  *    reports "the operation cannot be performed in the present state".  Drive
  *    one GPU from one process.
+ *  - Every device-wide wait is bounded (4 s; the environment variable
+ *    KP_WAIT_LIMIT_US, read when a context first uses the device, sets
+ *    another bound in microseconds).  A wait that exceeds it ends the launch
+ *    cleanly and the call reports KP_STATUS_ABORTED.
  *  - The library links the system HIP runtime.  In a process that also uses a
  *    second copy (PyTorch ships its own), load that copy first: loaded after
  *    this library, its initialisation leaves this library's first device

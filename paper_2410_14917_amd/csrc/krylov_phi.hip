@@ -15,6 +15,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -639,7 +640,14 @@ int device_setup(kp_ctx* ctx) {
   KP_HIP(ctx, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device));
   ctx->ncu = ncu;
   if (rate_khz <= 0) rate_khz = 100000;
-  ctx->wait_ticks = (int64_t)rate_khz * 1000 * 4;   // 4 s
+  // bound of every device-wide wait: 4 s, or KP_WAIT_LIMIT_US microseconds
+  // (read when the context first touches the device; for failure tests)
+  double limit_s = 4.0;
+  if (const char* e = std::getenv("KP_WAIT_LIMIT_US")) {
+    const double us = std::atof(e);
+    if (us > 0.0 && us < 4.0e6) limit_s = us * 1e-6;
+  }
+  ctx->wait_ticks = std::max<int64_t>(1, (int64_t)((double)rate_khz * 1000.0 * limit_s));
   return KP_OK;
 }
 
