@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "Arnoldi steps/s and phi_combo/s at N=1M,m=64; HBM GB/s vs peak; err vs FP64"
 KERNEL = "kp::k_run<double>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_run_allen_cahn_1024_traffic.txt")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_uneven_512_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2410_14917_amd", "csrc")
 
 
@@ -42,21 +43,22 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor the same
-    counter gives for a plain device copy of known size), or None when the
-    summary is missing or was taken on other kernel sources."""
+def measured_traffic(path=None, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch of the persistent kernel (or, with the batched
+    summary, per batched call) from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the factor the same counter gives for a plain
+    device copy of known size), or None when the summary is missing or was
+    taken on other kernel sources."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             for line in f:
                 if "=" in line and not line.lstrip().startswith("#"):
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("source_sha256") != kernel_source_hash():
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -380,6 +382,7 @@ def main():
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t0
         c4.close()
+        traffic4 = measured_traffic(BATCH_TRAFFIC_FILE, "hbm_bytes_per_call")
         result["batched"] = {
             "workload": f"{len(probs4)} advection-diffusion-reaction problems, sides U{{32..512}}, "
                         f"N total {sum(q.op.n for q in probs4)}, nu logU[1e-3,1e-1], r U[-1,1], "
@@ -392,6 +395,9 @@ def main():
             "arnoldi_steps_per_s": round(steps4 / (batch_ms * 1e-3), 1),
             "modelled_GBps": round(bytes4 / (batch_ms * 1e-3) / 1e9, 1),
             "frac": round(bytes4 / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": traffic4,
+            "measured_GBps": (round(traffic4 / (batch_ms * 1e-3) / 1e9, 1)
+                              if traffic4 else None),
             "plan_makespan_ms": round(1e3 * plan_s, 1),
             "plan_balanced_ms": round(1e3 * work_s / 256, 1),
             "status_ok": all(r["status"] == 0 for r in inf4),
