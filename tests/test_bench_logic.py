@@ -1,0 +1,38 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte count and the guard
+that reports measured HBM traffic only for the kernel sources it was taken on."""
+import bench
+
+
+def test_vector_passes_of_a_small_schedule_by_hand():
+    # p = 2, c = 1, one substep of m = 2.  Stage: b_0..b_2 read, u written (4).
+    # Step jj reads x_j, 2 columns of B, 1 field vector and jj basis columns,
+    # writes w, then the update reads w and jj + 1 columns and writes x_{jj+1}:
+    # 8 for jj = 0, 10 for jj = 1.  Column 0 written once (1).  Combine: 2
+    # columns read, 1 written (3).  The result written out (1).
+    assert bench.vectors_per_call([(0.1, 2)], 2, 1) == 4 + (8 + 10) + 1 + 3 + 1
+
+
+def test_vector_passes_of_the_benchmark_call():
+    # 14 substeps of m = 64 (the adaptive call at N = 1M): 64545 passes of
+    # N float64 = 541.4 GB, the figure the roofline divides by the launch time
+    n = 1024 * 1024
+    passes = bench.vectors_per_call([(0.1 / 14, 64)] * 14, 2, 1)
+    assert passes == 64545
+    assert passes * 8 * n == 541442703360
+
+
+def test_measured_traffic_only_for_matching_sources(tmp_path):
+    good = tmp_path / "good.txt"
+    good.write_text(f"# comment = ignored\nsource_sha256 = {bench.kernel_source_hash()}\n"
+                    "hbm_bytes_per_launch = 1.5e+11\nhbm_bytes_per_call = 2.5e+12\n")
+    stale = tmp_path / "stale.txt"
+    stale.write_text("source_sha256 = 00\nhbm_bytes_per_launch = 1.5e+11\n")
+    assert bench.measured_traffic(str(good)) == 1.5e11
+    assert bench.measured_traffic(str(good), "hbm_bytes_per_call") == 2.5e12
+    assert bench.measured_traffic(str(stale)) is None
+    assert bench.measured_traffic(str(tmp_path / "missing.txt")) is None
+
+
+def test_committed_summaries_match_the_current_sources():
+    assert bench.measured_traffic() is not None
+    assert bench.measured_traffic(bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call") is not None
