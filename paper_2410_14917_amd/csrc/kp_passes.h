@@ -524,10 +524,31 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
 // The older columns are visited kCh at a time, software-pipelined: the loads
 // of the next chunk are in flight while the wave reduces the current one.
 
-// Per-wave sums of x_i . x and x_i . w for the kCh columns of one chunk
+// Columns of one chunk are held as loaded (a float basis stays packed until
+// it is multiplied), so that a float chunk of 2 * kCh columns takes the
+// registers of a double chunk of kCh: the float pass keeps as many bytes in
+// flight as the double one.  Each column's sums are formed and recorded on
+// their own, so the chunk width does not change any result.
+template <typename TB> struct Raw;
+template <> struct Raw<double> {
+  typedef double2 type;
+  static constexpr int kCols = kCh;
+  __device__ static double2 load(const double* base, uint32_t byte_off) {
+    return load_at(base, byte_off);
+  }
+};
+template <> struct Raw<float> {
+  typedef kp_f2 type;
+  static constexpr int kCols = 2 * kCh;
+  __device__ static kp_f2 load(const float* base, uint32_t byte_off) {
+    return *(const KP_GLOBAL kp_f2*)((const KP_GLOBAL char*)base + byte_off);
+  }
+};
+
+// Per-wave sums of x_i . x and x_i . w for the C columns of one chunk
 // (columns past nc repeat the last one and are not recorded).
-template <int C>
-__device__ inline void dots_chunk(const double2 (&v)[C][kR], const double2* xv,
+template <int C, typename R>
+__device__ inline void dots_chunk(const R (&v)[C][kR], const double2* xv,
                                   const double2* wv2, int i0, int nc, double* sacc) {
   const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
 #pragma unroll
@@ -535,8 +556,9 @@ __device__ inline void dots_chunk(const double2 (&v)[C][kR], const double2* xv,
     double ax = 0.0, aw = 0.0;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-      ax += v[c][r].x * xv[r].x + v[c][r].y * xv[r].y;
-      aw += v[c][r].x * wv2[r].x + v[c][r].y * wv2[r].y;
+      const double vx = (double)v[c][r].x, vy = (double)v[c][r].y;
+      ax += vx * xv[r].x + vy * xv[r].y;
+      aw += vx * wv2[r].x + vy * wv2[r].y;
     }
     if (c < nc) {
       ax = wave_sum(ax);
@@ -551,12 +573,12 @@ __device__ inline void dots_chunk(const double2 (&v)[C][kR], const double2* xv,
 
 template <typename TB, int C>
 __device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, int nc,
-                                  const uint32_t* lo, double2 (&v)[C][kR]) {
+                                  const uint32_t* lo, typename Raw<TB>::type (&v)[C][kR]) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const TB* vc = uniform_ptr(V + (int64_t)(i0 + min(c, nc - 1)) * ld + t0);
 #pragma unroll
-    for (int r = 0; r < kR; ++r) v[c][r] = load_at(vc, lo[r] * (uint32_t)sizeof(TB));
+    for (int r = 0; r < kR; ++r) v[c][r] = Raw<TB>::load(vc, lo[r] * (uint32_t)sizeof(TB));
   }
 }
 
@@ -592,7 +614,8 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       bool ok[kR];
       tile_pairs(q0, pend, lo, ok);
       double2 xv[kR], wv2[kR];
-      double2 va[kCh][kR], vb[kCh][kR];
+      constexpr int CC = Raw<TB>::kCols;
+      typename Raw<TB>::type va[CC][kR], vb[CC][kR];
 #pragma unroll
       for (int r = 0; r < kR; ++r) xv[r] = x.pair(t0 + lo[r]);
       aug_tile<TB, HL>(a, o, sg, x, hl, t0, lo, tc, wv2);
@@ -615,15 +638,15 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
         sww += wv2[r].x * wv2[r].x + wv2[r].y * wv2[r].y;
       }
       // x_i . x and x_i . w for the older columns, two chunks in flight
-      if (jj > 0) load_chunk<TB, kCh>(V, ld, t0, 0, min(kCh, jj), lo, va);
-      for (int i0 = 0; i0 < jj; i0 += 2 * kCh) {
-        const int i1 = i0 + kCh;
-        if (i1 < jj) load_chunk<TB, kCh>(V, ld, t0, i1, min(kCh, jj - i1), lo, vb);
-        dots_chunk<kCh>(va, xv, wv2, i0, min(kCh, jj - i0), sacc);
+      if (jj > 0) load_chunk<TB, CC>(V, ld, t0, 0, min(CC, jj), lo, va);
+      for (int i0 = 0; i0 < jj; i0 += 2 * CC) {
+        const int i1 = i0 + CC;
+        if (i1 < jj) load_chunk<TB, CC>(V, ld, t0, i1, min(CC, jj - i1), lo, vb);
+        dots_chunk<CC>(va, xv, wv2, i0, min(CC, jj - i0), sacc);
         if (i1 >= jj) break;
-        const int i2 = i1 + kCh;
-        if (i2 < jj) load_chunk<TB, kCh>(V, ld, t0, i2, min(kCh, jj - i2), lo, va);
-        dots_chunk<kCh>(vb, xv, wv2, i1, min(kCh, jj - i1), sacc);
+        const int i2 = i1 + CC;
+        if (i2 < jj) load_chunk<TB, CC>(V, ld, t0, i2, min(CC, jj - i2), lo, va);
+        dots_chunk<CC>(vb, xv, wv2, i1, min(CC, jj - i1), sacc);
       }
     }
   }
