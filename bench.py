@@ -72,7 +72,7 @@ def basis_bytes_per_call(schedule, p, c, n, s):
     reads p+1 columns and writes u (8); the last combine writes out (8)."""
     total = 8 * ((p + 1) + 1)
     for _, m in schedule:
-        total += sum(s * (2 * jj + 4) + 8 * (p + c) for jj in range(m)) + s + s * m + 8
+        total += sum(s * (2 * jj + 5) + 8 * (p + c) for jj in range(m)) + s + s * m + 8
     return (total + 8) * n
 
 

@@ -36,3 +36,21 @@ def test_measured_traffic_only_for_matching_sources(tmp_path):
 def test_committed_summaries_match_the_current_sources():
     assert bench.measured_traffic() is not None
     assert bench.measured_traffic(bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call") is not None
+
+
+def test_basis_bytes_of_a_small_schedule_by_hand():
+    # 4-byte basis, p = 2, c = 1, N = 1, one substep of m = 2.  Stage: 3 float64
+    # columns read, u written (32).  Step jj: x_j, jj older columns and w
+    # written (basis), 2 columns of B and 1 field (float64), then w, jj + 1
+    # columns and x_{jj+1} written (basis): 4 * 5 + 24 = 44 for jj = 0 and
+    # 4 * 7 + 24 = 52 for jj = 1.  Column 0 written (4).  Combine: 2 columns
+    # read (8), u written (8).  The result written out (8).
+    assert bench.basis_bytes_per_call([(0.1, 2)], 2, 1, 1, 4) == 32 + 44 + 52 + 4 + 16 + 8
+
+
+def test_basis_bytes_with_float64_basis_match_the_vector_passes():
+    for sched, p, c in (([(0.1, 2)], 2, 1), ([(0.05, 64)] * 3 + [(0.02, 17)], 2, 2),
+                        ([(0.1, 1)], 0, 0), ([(0.01, 48)] * 5, 3, 0)):
+        n = 1000
+        assert bench.basis_bytes_per_call(sched, p, c, n, 8) == \
+            bench.vectors_per_call(sched, p, c) * 8 * n
