@@ -455,6 +455,13 @@ __global__ __launch_bounds__(256) void k_dot_final(const double* part, double* o
   if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Zero fill of n doubles (a kernel rather than a memset node, so that a
+// caller may capture the enqueuing call in a graph and replay it).
+__global__ __launch_bounds__(256) void k_zero(double* x, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) x[e] = 0.0;
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -1238,7 +1245,12 @@ int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t 
     // B_k = [0, ..., 0, g] (k zero columns), a view of W from column p - k
     kp_op At = *A;
     At.transpose = A->transpose ? 0 : 1;
-    if (p > 0) KP_HIP(ctx, hipMemsetAsync(W, 0, sizeof(double) * (size_t)p * N, ctx->stream));
+    if (p > 0) {
+      const int64_t nz = (int64_t)p * N;
+      hipLaunchKernelGGL(kp::k_zero, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 4096)),
+                         dim3(256), 0, ctx->stream, W, nz);
+      KP_HIP(ctx, hipGetLastError());
+    }
     KP_HIP(ctx, hipMemcpyAsync(W + (size_t)p * N, g, sizeof(double) * N, hipMemcpyDeviceToDevice,
                                ctx->stream));
     for (int k = 0; k <= p; ++k) {
