@@ -158,3 +158,29 @@ def test_null_context_is_invalid():
         == _lib.KP_EINVAL
     assert lib.kp_destroy(None) == _lib.KP_EINVAL
     assert lib.kp_create(None, None) == _lib.KP_EINVAL
+
+
+def test_batched_rejects_empty_and_missing_arrays():
+    """nprob < 1 and missing host arrays are refused before any device work."""
+    lib, h, rc = _ctx()
+    assert rc == 0
+    try:
+        op = _op()
+        ops = (_lib.KpOp * 1)(op)
+        Bp = (ctypes.c_void_p * 1)(FAKE.value)
+        ps = (ctypes.c_int32 * 1)(2)
+        lds = (ctypes.c_int64 * 1)(64)
+        hs = (ctypes.c_double * 1)(0.1)
+        outs = (ctypes.c_void_p * 1)(FAKE2.value)
+        full = [ops, Bp, ps, lds, hs, outs]
+        for nprob in (0, -3):
+            assert lib.kp_phi_combo_batched(h, nprob, ops, Bp, ps, lds, hs, 1e-8, 10, outs,
+                                            None) == _lib.KP_EINVAL
+        for miss in range(len(full)):
+            args = [None if i == miss else a for i, a in enumerate(full)]
+            assert lib.kp_phi_combo_batched(h, 1, args[0], args[1], args[2], args[3], args[4],
+                                            1e-8, 10, args[5], None) == _lib.KP_EINVAL
+        assert lib.kp_phi_combo_batched(None, 1, ops, Bp, ps, lds, hs, 1e-8, 10, outs,
+                                        None) == _lib.KP_EINVAL
+    finally:
+        lib.kp_destroy(h)
