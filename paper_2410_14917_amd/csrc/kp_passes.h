@@ -521,8 +521,9 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
 // this workgroup's row of the step buffer of the phase's barrier; own: the
 // leader's LDS copy of its sums (nullptr in the other workgroups).
 //
-// The older columns are visited kCh at a time, software-pipelined: the loads
-// of the next chunk are in flight while the wave reduces the current one.
+// The older columns are visited a chunk at a time (kCh columns of a double
+// basis, 2 * kCh of a float one), software-pipelined: the loads of the next
+// chunk are in flight while the wave reduces the current one.
 
 // Columns of one chunk are held as loaded (a float basis stays packed until
 // it is multiplied), so that a float chunk of 2 * kCh columns takes the
