@@ -1,8 +1,8 @@
 """Arnoldi processes (oracle, test infrastructure).
 
-Two processes build an orthonormal basis V and Hessenberg H of the Krylov space
-K_m(A, b) with A V_m = V_m H_m + h_{m+1,m} v_{m+1} e_m^T (Section 2.2, eq.
-arnoldidecomp1):
+Three processes build a basis V and Hessenberg H of the Krylov space K_m(A, b)
+with A V_m = V_m H_m + h_{m+1,m} v_{m+1} e_m^T (Section 2.2, eq.
+arnoldidecomp1); the first two keep V orthonormal:
 
 * MGSArnoldi: Arnoldi with modified Gram-Schmidt (Algorithm 1): after each
   matrix-vector product, the new vector is orthogonalised against v_1..v_j one
@@ -32,6 +32,15 @@ Readings of the printed Algorithm 4 (garbled in places) used here:
     norm is <= eps_bd * ||w||.
   * The last subdiagonal H_{m+1,m} is the norm of the projected (not yet
     estimate-normalised) vector v_{m+1}.
+
+* IOPArnoldi: the incomplete orthogonalisation process (Section 2.3.1) in its
+  classical Gram-Schmidt form, ioCGS, the baseline of the paper's runtime
+  ratios (Section 4.2): the new vector is orthogonalised against only the
+  previous `window` basis vectors (two, as in KIOPS), all of their inner
+  products taken from the same vector (one reduction, the classical form),
+  then normalised by its norm (a second reduction).  H keeps its Hessenberg
+  shape but has at most `window` entries above the subdiagonal per column,
+  and V is not orthonormal, so V_m^T A V_m differs from H_m.
 """
 from __future__ import annotations
 
@@ -65,6 +74,47 @@ class MGSArnoldi:
                 hij = float(self.V[:, i] @ w)
                 self.H[i, j] = hij
                 w -= hij * self.V[:, i]
+            nrm = float(np.linalg.norm(w))
+            self.j += 1
+            if nrm <= self.eps_bd * wnorm:
+                self.H[j + 1, j] = 0.0
+                self.breakdown = True
+                break
+            self.H[j + 1, j] = nrm
+            self.V[:, j + 1] = w / nrm
+        return self.j
+
+
+class IOPArnoldi:
+    """Incomplete orthogonalisation with classical Gram-Schmidt (ioCGS),
+    Section 2.3.1.  Same interface as MGSArnoldi."""
+
+    def __init__(self, apply, b: np.ndarray, m_cap: int, window: int = 2,
+                 eps_bd: float = 1e-12):
+        if window < 1:
+            raise ValueError(window)
+        self.apply = apply
+        self.window = window
+        self.n = len(b)
+        self.V = np.zeros((self.n, m_cap + 1), order="F")
+        self.H = np.zeros((m_cap + 1, m_cap))
+        self.beta = float(np.linalg.norm(b))
+        self.eps_bd = eps_bd
+        self.j = 0
+        self.breakdown = False
+        if self.beta > 0.0:
+            self.V[:, 0] = b / self.beta
+
+    def extend(self, m: int) -> int:
+        """Run steps until j == m or lucky breakdown; returns j."""
+        while self.j < m and not self.breakdown:
+            j = self.j                          # 0-based column of v_{j+1}
+            w = self.apply(self.V[:, j])
+            wnorm = float(np.linalg.norm(w))
+            lo = max(0, j - self.window + 1)
+            h = self.V[:, lo:j + 1].T @ w       # all window products from w
+            self.H[lo:j + 1, j] = h
+            w = w - self.V[:, lo:j + 1] @ h
             nrm = float(np.linalg.norm(w))
             self.j += 1
             if nrm <= self.eps_bd * wnorm:

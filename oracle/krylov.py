@@ -28,6 +28,13 @@ adaptive  the substep controller below.  The paper delegates it to KIOPS and
               the small exponential is recomputed);
             tau update: tau *= clamp(0.9 * omega^(-1/(q+1)), 0.2, 4),
               q = ceil(m/4), omega = 0 -> factor 4;
+            controller="pi" (the PI step-size control that Section 5 names as
+              future work) replaces the factor after an accepted substep by
+              clamp(0.9 * omega^(-0.7/(q+1)) * omega_prev^(0.4/(q+1)), 0.2, 4),
+              omega_prev that of the previous accepted substep (the
+              Gustafsson PI gains of Hairer and Wanner, Solving ODEs II,
+              Section IV.2); the first accepted substep and every rejection
+              use the power law above;
             lucky breakdown: the space is invariant, tau = h - t, accept;
             the last substep is clipped to end exactly at h.
 """
@@ -40,12 +47,27 @@ from typing import List, Tuple
 import numpy as np
 
 from . import operators
-from .arnoldi import HybridArnoldi, MGSArnoldi
+from .arnoldi import HybridArnoldi, IOPArnoldi, MGSArnoldi
 from .phi import expm_taylor
 
 STATUS_OK, STATUS_NOT_CONVERGED, STATUS_NONFINITE = 0, 1, 2
 
 F_SAFE, F_MIN, F_MAX = 0.9, 0.2, 4.0
+PI_KI, PI_KP = 0.7, 0.4
+
+
+def step_factor(omega: float, m: int, omega_prev: float = 0.0, controller: str = "power"):
+    """Step-size factor after a substep of dimension m with normalised error
+    omega (accept iff omega <= 1).  omega_prev > 0 with controller "pi":
+    the proportional-integral law; otherwise the power law."""
+    if omega == 0.0:
+        return F_MAX
+    q = (m + 3) // 4
+    if controller == "pi" and omega_prev > 0.0:
+        f = F_SAFE * omega ** (-PI_KI / (q + 1)) * omega_prev ** (PI_KP / (q + 1))
+    else:
+        f = F_SAFE * omega ** (-1.0 / (q + 1))
+    return min(F_MAX, max(F_MIN, f))
 
 
 def balance_scale(B: np.ndarray, p: int) -> float:
@@ -106,11 +128,15 @@ class Info:
 def _make_arnoldi(orth, apply, w, m_cap, tform, delta, eps_bd):
     if orth == "mgs":
         return MGSArnoldi(apply, w, m_cap, eps_bd=eps_bd)
+    if orth == "iop":
+        return IOPArnoldi(apply, w, m_cap, window=2, eps_bd=eps_bd)
+    if orth != "hybrid":
+        raise ValueError(orth)
     return HybridArnoldi(apply, w, m_cap, tform=tform, delta=delta, eps_bd=eps_bd)
 
 
 def _basis(arn, m):
-    if isinstance(arn, MGSArnoldi):
+    if isinstance(arn, (MGSArnoldi, IOPArnoldi)):
         return arn.V[:, :m]
     return arn.basis()[:, :m]
 
@@ -119,7 +145,7 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
           fixed_m: int = 0, fixed_substeps: int = 0, orth: str = "mgs",
           tform: str = "gsmgs", max_substeps: int = 2000, delta: float = 1e-10,
           eps_bd: float = 1e-12, want_orth_loss=False, m_init: int = 16,
-          tau_init: float = 0.0, schedule=None):
+          tau_init: float = 0.0, schedule=None, controller: str = "power"):
     """exp(h M) w for the operator M given by apply(x) = M x, by substepped
     Krylov projections with the schedules above.  Returns (vector, Info).
 
@@ -141,6 +167,9 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
     else:
         m = min(m_init, m_max)
         tau = min(tau_init, h) if tau_init > 0.0 else h
+    if controller not in ("power", "pi"):
+        raise ValueError(controller)
+    omega_prev = 0.0                               # of the last accepted substep
     t = 0.0
     while t < h:
         if info.substeps >= (nsub if fixed else max_substeps):
@@ -151,7 +180,7 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
             tau = min(tau, h - t)
         arn = _make_arnoldi(orth, apply, w, m_max if not fixed else m, tform,
                             delta, eps_bd)
-        if orth == "mgs" and arn.beta == 0.0:
+        if orth in ("mgs", "iop") and arn.beta == 0.0:
             break                                  # zero stays zero
         mb = arn.extend(m)
         beta = arn.beta
@@ -190,8 +219,7 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
                 mb = arn.extend(m)
                 info.arnoldi_steps += mb - before
                 continue
-            q = (mb + 3) // 4
-            tau = tau * min(F_MAX, max(F_MIN, F_SAFE * omega ** (-1.0 / (q + 1))))
+            tau = tau * step_factor(omega, mb)
             if tau <= 1e-14 * h:
                 info.status = STATUS_NOT_CONVERGED
                 return w.copy(), info
@@ -211,10 +239,8 @@ def expmv(apply, w: np.ndarray, h: float, tol: float = 1e-8, m_max: int = 64,
             t = h if info.substeps == nsub else t + tau
         else:
             t = h if tau >= h - t else t + tau
-            q = (mb + 3) // 4
-            fac = F_MAX if omega == 0.0 else min(
-                F_MAX, max(F_MIN, F_SAFE * omega ** (-1.0 / (q + 1))))
-            tau = tau * fac
+            tau = tau * step_factor(omega, mb, omega_prev, controller)
+            omega_prev = omega
     return w.copy(), info
 
 
@@ -222,7 +248,7 @@ def _replay(apply, w, schedule, orth, tform, delta, eps_bd, info):
     """The substeps of a given schedule; see expmv."""
     for tau, m_i in schedule:
         arn = _make_arnoldi(orth, apply, w, int(m_i), tform, delta, eps_bd)
-        if orth == "mgs" and arn.beta == 0.0:
+        if orth in ("mgs", "iop") and arn.beta == 0.0:
             break
         mb = arn.extend(int(m_i))
         beta = arn.beta
@@ -249,9 +275,12 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
               m_max: int = 64, fixed_m: int = 0, fixed_substeps: int = 0,
               orth: str = "mgs", tform: str = "gsmgs", max_substeps: int = 2000,
               delta: float = 1e-10, eps_bd: float = 1e-12, want_orth_loss=False,
-              mu: float = None, m_init: int = 16, tau_init: float = 0.0, schedule=None):
-    """Returns (y, Info).  orth: 'mgs' (Algorithm 1) or 'hybrid' (Algorithm 4);
-    schedule: replay the given accepted substeps (see expmv)."""
+              mu: float = None, m_init: int = 16, tau_init: float = 0.0, schedule=None,
+              controller: str = "power"):
+    """Returns (y, Info).  orth: 'mgs' (Algorithm 1), 'hybrid' (Algorithm 4)
+    or 'iop' (ioCGS, Section 2.3.1); schedule: replay the given accepted
+    substeps (see expmv); controller: 'power' or 'pi' (see the module
+    docstring)."""
     n = op.n
     B = np.asarray(B, dtype=np.float64)
     if not np.all(np.isfinite(B[:, :p + 1])):
@@ -271,5 +300,5 @@ def phi_combo(op, B: np.ndarray, h: float, p: int, tol: float = 1e-8,
                     fixed_substeps=fixed_substeps, orth=orth, tform=tform,
                     max_substeps=max_substeps, delta=delta, eps_bd=eps_bd,
                     want_orth_loss=want_orth_loss, m_init=m_init, tau_init=tau_init,
-                    schedule=schedule)
+                    schedule=schedule, controller=controller)
     return r[:n].copy(), info

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import arnoldi, krylov, operators
+from oracle import arnoldi, krylov, operators, phi
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -193,3 +193,85 @@ def test_orthogonality_loss_ordering_on_stiff_problem():
     loss["mgs"] = np.linalg.norm(np.eye(40) - m.V[:, :40].T @ m.V[:, :40], 2)
     assert loss["gsmgs"] <= loss["cwy"]
     assert max(loss.values()) < 1e-8
+
+
+# ---- incomplete orthogonalisation (ioCGS, Section 2.3.1) --------------------
+
+def _symmetric_problem(seed=51, nx=11, ny=9):
+    """Diffusion + reaction + a diagonal field, p = 0: A is symmetric."""
+    rng = np.random.default_rng(seed)
+    op = W.Operator(kind=W.OP_ADR, nx=nx, ny=ny, nu=0.02, react=-0.4,
+                    field0=rng.uniform(-1.0, 1.0, nx * ny))
+    b = rng.standard_normal(op.n)
+    return op, (lambda x: operators.apply(op, x)), b
+
+
+def test_iop_on_symmetric_operator_is_lanczos():
+    """For symmetric A the full Arnoldi process has a tridiagonal H (the
+    Lanczos recurrence), so orthogonalising against the previous two vectors
+    gives the same H and V as MGS (until orthogonality is lost)."""
+    op, apply, b = _symmetric_problem()
+    A = operators.dense(op)
+    assert np.allclose(A, A.T)
+    m = 12
+    a = arnoldi.MGSArnoldi(apply, b, m)
+    a.extend(m)
+    c = arnoldi.IOPArnoldi(apply, b, m, window=2)
+    c.extend(m)
+    assert np.allclose(np.triu(a.H[:m + 1, :m], 2), 0.0, atol=1e-12 * np.abs(a.H).max())
+    assert np.linalg.norm(c.H[:m + 1, :m] - a.H[:m + 1, :m]) <= 1e-10 * np.linalg.norm(a.H)
+    assert np.linalg.norm(c.V[:, :m + 1] - a.V[:, :m + 1]) <= 1e-9
+
+
+def test_iop_with_full_window_is_classical_gram_schmidt():
+    """A window of at least m is classical Gram-Schmidt against the whole
+    basis: the same Hessenberg matrix as MGS in exact arithmetic; a window of
+    one leaves the entries above the diagonal zero."""
+    pr, apply, z = _problem(seed=52, nx=8, ny=6)
+    m = 8
+    a = arnoldi.MGSArnoldi(apply, z, m)
+    a.extend(m)
+    c = arnoldi.IOPArnoldi(apply, z, m, window=m)
+    c.extend(m)
+    assert np.linalg.norm(c.H[:m + 1, :m] - a.H[:m + 1, :m]) <= 1e-10 * np.linalg.norm(a.H)
+    d = arnoldi.IOPArnoldi(apply, z, m, window=1)
+    d.extend(m)
+    assert np.allclose(np.triu(d.H[:m + 1, :m], 1), 0.0)
+
+
+def test_iop_arnoldi_relation_without_orthogonality():
+    """On a non-normal operator the two-vector window still satisfies
+    A V_m = V_{m+1} Hbar (each column is built that way), each new vector is
+    orthogonal to its window, but V^T V is far from I."""
+    pr, apply, z = _problem(seed=53, nx=10, ny=8)
+    m = 20
+    c = arnoldi.IOPArnoldi(apply, z, m, window=2)
+    assert c.extend(m) == m
+    V, H = c.V[:, :m + 1], c.H[:m + 1, :m]
+    A = _aug_dense(apply, len(z))
+    assert np.linalg.norm(A @ V[:, :m] - V @ H) <= 1e-12 * np.linalg.norm(A, 2)
+    assert np.allclose(np.triu(H, 2), 0.0) and np.allclose(np.tril(H, -2), 0.0)
+    for j in range(1, m + 1):
+        lo = max(0, j - 2)
+        assert np.all(np.abs(V[:, lo:j].T @ V[:, j]) <= 1e-12)
+    assert np.linalg.norm(np.eye(m + 1) - V.T @ V, 2) > 1e-3
+
+
+def test_iop_exact_at_invariant_subspace():
+    """A diagonal operator with d distinct values and p = 0 (a symmetric
+    matrix, so the two-vector window is the Lanczos recurrence): the Krylov
+    space is invariant after d steps (lucky breakdown), where A V = V H makes
+    V exp(tau H) e_1 exact."""
+    d_vals = np.array([-2.0, -0.7, 0.3, 0.9])
+    nx, ny = 8, 5
+    diag = d_vals[np.random.default_rng(54).integers(0, len(d_vals), nx * ny)]
+    op = W.Operator(kind=W.OP_ADR, nx=nx, ny=ny, field0=diag)
+    p = 0
+    B = np.random.default_rng(55).standard_normal((op.n, p + 1))
+    y, info = krylov.phi_combo(op, B, 0.4, p, fixed_m=12, fixed_substeps=1, m_max=12,
+                               orth="iop")
+    assert info.breakdowns == 1 and info.m_last == len(d_vals)
+    ref = np.zeros(op.n)
+    for k in range(p + 1):
+        ref += 0.4 ** k * np.array([phi.phi_scalar(k, 0.4 * d) for d in diag]) * B[:, k]
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)

@@ -170,3 +170,47 @@ def test_replay_of_an_adaptive_schedule_reproduces_the_run():
                                    schedule=info_a.schedule)
     assert info_r.schedule == info_a.schedule
     assert rel(y_r, y_a) <= 1e-13
+
+
+# ---- ioCGS (Section 2.3.1) and the PI substep controller (Conclusion) -------
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_iop_adaptive_meets_tolerance_against_closed_form(tol):
+    """The incomplete process in the same controller reaches the DFT closed
+    form within 10 tol on a non-normal advection-diffusion operator."""
+    op = W.Operator(kind=W.OP_ADR, nx=48, ny=40, nu=0.1, ax=1.0, ay=0.5, react=-0.5)
+    B = np.random.default_rng(42).standard_normal((op.n, 4))
+    ref = closed_form.adr_phi_combo(op, B, 0.1, 3)
+    y, info = krylov.phi_combo(op, B, 0.1, 3, tol=tol, m_max=24, orth="iop")
+    assert info.status == krylov.STATUS_OK and info.substeps >= 2
+    assert rel(y, ref) <= 10 * tol
+
+
+@pytest.mark.parametrize("orth", ["mgs", "hybrid", "iop"])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_pi_controller_meets_tolerance_against_closed_form(orth, tol):
+    op = W.Operator(kind=W.OP_ADR, nx=48, ny=40, nu=0.1, ax=1.0, ay=0.5, react=-0.5)
+    B = np.random.default_rng(42).standard_normal((op.n, 4))
+    ref = closed_form.adr_phi_combo(op, B, 0.1, 3)
+    y, info = krylov.phi_combo(op, B, 0.1, 3, tol=tol, m_max=24, orth=orth, controller="pi")
+    assert info.status == krylov.STATUS_OK and info.substeps >= 2
+    assert rel(y, ref) <= 10 * tol
+
+
+def test_pi_controller_uses_the_previous_error():
+    """The PI factor depends on the previous accepted substep's error: with
+    omega_prev = 1 it is the integral part alone; a more accurate previous
+    substep (the error growing) gives a smaller factor; clipped to [0.2, 4]."""
+    for m in (8, 33, 64):
+        for om in (1e-3, 0.3, 0.9):
+            f_pow = krylov.step_factor(om, m)
+            q = (m + 3) // 4
+            assert krylov.step_factor(om, m, 1.0, "pi") == pytest.approx(
+                min(4.0, 0.9 * om ** (-0.7 / (q + 1))), rel=1e-15)
+            if krylov.step_factor(om, m, 1.0, "pi") < 4.0:
+                assert krylov.step_factor(om, m, 0.5, "pi") < krylov.step_factor(om, m, 1.0, "pi")
+            assert 0.2 <= f_pow <= 4.0
+        assert krylov.step_factor(0.0, m, 0.5, "pi") == 4.0
+        assert krylov.step_factor(1e30, m) == 0.2
+    # without a previous accepted substep the PI controller is the power law
+    assert krylov.step_factor(0.3, 16, 0.0, "pi") == krylov.step_factor(0.3, 16)
