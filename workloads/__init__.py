@@ -210,3 +210,70 @@ def random_problem(seed: int, kind: int = OP_ADR, nx: int = 16, ny: int = 12,
     B = gaussian_columns(rng, op.n, p + 1)
     return Problem(op=op, B=B, h=h, p=p, m_max=m_max, tol=tol, seed=seed,
                    name=f"rand-{kind}-{nx}x{ny}")
+
+
+# ---- nonlinear problems of the exponential integrators (Section 4.3) ---------
+#
+# u' = f(u) on a periodic grid (point (ix, iy) at index iy*nx + ix):
+#   RHS_ALLEN_CAHN  f(u) = nu Lap u + u - u^3
+#   RHS_ADR         f(u) = nu Lap u - ax Dx u - ay Dy u + gamma u (u - 1/2) (1 - u)
+# (same numbering as the C header's KP_RHS_* constants).  The paper's
+# problems have no-flow / Neumann boundaries; these are their periodic
+# stand-ins, with the paper's coefficients and initial states.
+RHS_ALLEN_CAHN = 0
+RHS_ADR = 1
+
+
+@dataclasses.dataclass
+class Rhs:
+    kind: int
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    nu: float = 0.0
+    ax: float = 0.0
+    ay: float = 0.0
+    gamma: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+
+@dataclasses.dataclass
+class Ivp:
+    rhs: Rhs
+    u0: np.ndarray
+    dt: float
+    nsteps: int
+    tol: float
+    m_max: int = 64
+    name: str = ""
+
+
+def ivp_allen_cahn(side: int = 2000, dt: float = 1e-2, nsteps: int = 2,
+                   tol: float = 1e-12) -> Ivp:
+    """Allen-Cahn on [-1, 1]^2 (Section 4.3): epsilon = 0.1, initial state
+    0.1 + 0.1 cos(2 pi x) cos(2 pi y), dt = 1e-2 (t_f = 0.02: two steps)."""
+    dx = 2.0 / side
+    x = -1.0 + dx * np.arange(side)
+    X, Y = np.meshgrid(x, x)
+    u0 = 0.1 + 0.1 * np.cos(2.0 * math.pi * X) * np.cos(2.0 * math.pi * Y)
+    return Ivp(Rhs(RHS_ALLEN_CAHN, side, side, dx, dx, nu=0.1), np.ascontiguousarray(u0.reshape(-1)),
+               dt, nsteps, tol, name=f"allen-cahn{side}")
+
+
+def ivp_adr(side: int = 2000, dt: float = 1e-2, nsteps: int = 10, tol: float = 1e-12,
+            gamma: float = 100.0) -> Ivp:
+    """Advection-diffusion-reaction on [0, 1]^2 (Section 4.3): epsilon = 1e-2,
+    alpha = -6 (f = eps Lap u - alpha (u_x + u_y) + gamma u (u - 1/2)(1 - u)),
+    initial state 0.3 + 256 (x y (1 - x)(1 - y))^2, dt = 1e-2 (t_f = 0.1);
+    gamma is not printed, 100 is taken."""
+    dx = 1.0 / side
+    x = dx * np.arange(side)
+    X, Y = np.meshgrid(x, x)
+    u0 = 0.3 + 256.0 * (X * Y * (1.0 - X) * (1.0 - Y)) ** 2
+    return Ivp(Rhs(RHS_ADR, side, side, dx, dx, nu=1e-2, ax=-6.0, ay=-6.0, gamma=gamma),
+               np.ascontiguousarray(u0.reshape(-1)), dt, nsteps, tol, name=f"adr{side}")
+
