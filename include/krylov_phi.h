@@ -67,10 +67,27 @@ extern "C" {
 #define KP_STATUS_NONFINITE     2  /* NaN/Inf in the input or the iteration */
 #define KP_STATUS_ABORTED       3  /* a device-wide wait exceeded its limit */
 
-/* ---- orthogonalisation (correction matrix T ~ (V^T V)^{-1}) ------------- */
+/* ---- orthogonalisation ---------------------------------------------------
+ * The hybrid one-reduction forms of Algorithm 4 (correction matrix
+ * T ~ (V^T V)^{-1}): one grid-wide reduction per Arnoldi step. */
 #define KP_ORTH_H_GSMGS 0  /* Algorithm 7: T = M^{-1}[I + N M^{-1}], default */
 #define KP_ORTH_H_CWY   1  /* Algorithm 5: T = (I + L)^{-1} by recursion    */
 #define KP_ORTH_H_NCWY  2  /* Algorithm 6: T = I - L (Neumann, two terms)   */
+/* The comparators of Sections 2.3 and 4.2, in the same persistent kernel and
+ * controller: */
+#define KP_ORTH_MGS     3  /* Algorithm 1: modified Gram-Schmidt, j + 1 grid
+                              reductions at step j (j inner products, 1 norm) */
+#define KP_ORTH_IOCGS   4  /* ioCGS (Section 2.3.1): classical Gram-Schmidt
+                              against the previous two vectors only, then the
+                              norm: 2 grid reductions per step; V is not
+                              orthonormal */
+
+/* ---- substep-size controller -------------------------------------------- */
+#define KP_CTRL_POWER 0    /* tau *= clamp(0.9 w^(-1/(q+1)), 0.2, 4) (default) */
+#define KP_CTRL_PI    1    /* proportional-integral control after accepted
+                              substeps (the Conclusion's future work; gains of
+                              Gustafsson's PI controller): tau *= clamp(0.9
+                              w^(-0.7/(q+1)) w_prev^(0.4/(q+1)), 0.2, 4) */
 
 /* ---- operator kinds (matrix-free, 2D periodic, second-order FD) --------- */
 #define KP_OP_ADR         0 /* nu Lap u - ax Dx u - ay Dy u + react u (+ field0 .* u) */
@@ -127,6 +144,12 @@ typedef struct kp_config {
                                 0 -> 1e-12                                     */
     double  tau_init;        /* first substep length of the adaptive controller;
                                 0 -> h (clipped to h)                           */
+    int32_t controller;      /* KP_CTRL_*, default KP_CTRL_POWER              */
+    int32_t rows_per_wg;     /* grid rows owned by each workgroup of a single
+                                call; 0 -> automatic (at least 4096 elements per
+                                workgroup, one workgroup per CU at most).  A
+                                smaller value spreads a small grid over more
+                                CUs (raised to what the CU count needs).      */
 } kp_config;
 
 /* Outcome of a call (filled after the stream is synchronised). */
@@ -273,6 +296,49 @@ int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops,
                          const double* h, double tol, int32_t m_max,
                          double* const* out, kp_info* infos);
 
+/*
+ * Exponential integrators (Section 4.1) for u' = f(u) on a periodic grid,
+ * each step one or two phi combinations of the Jacobian J_n = f'(u_n):
+ *   KP_EPI4, KP_EPI5 (multistep, the coefficient matrices A_4, A_5 printed
+ *     in Section 4.1; P = 2, 3 previous states):
+ *       u_{n+1} = u_n + phi_1(h J_n) h f_n + sum_m phi_m(h J_n) v_m,
+ *       v_m = sum_i alpha_{m,i} h R(u_{n-i}),  R(v) = f(v) - f_n - J_n (v - u_n);
+ *     one kp_phi_combo per step (b_1 = f_n, b_m = v_m / h^m).  The first P
+ *     steps are SRERK3 steps, each taken as start_substeps equal substeps.
+ *   KP_SRERK3: z = u_n + phi_1(3/4 h J_n) 3/4 h f_n,
+ *       u_{n+1} = u_n + phi_1(h J_n) h f_n + phi_3(h J_n) 32/9 h R(z):
+ *     two calls per step.
+ * Right-hand sides (kp_rhs, second-order differences as the operators):
+ *   KP_RHS_ALLEN_CAHN  f = nu Lap u + u - u^3 (J: KP_OP_ALLEN_CAHN, field u_n)
+ *   KP_RHS_ADR         f = nu Lap u - ax Dx u - ay Dy u + gamma u (u - 1/2)(1 - u)
+ *                      (J: KP_OP_ADR with the field gamma (-3 u_n^2 + 3 u_n - 1/2))
+ *   u     : device, nx*ny doubles: the initial state, overwritten with the state
+ *           after nsteps steps of size dt.
+ *   tol, m_max: of every phi combination (the context's configuration applies:
+ *           orthogonalisation, controller, basis type, fixed schedule).
+ *   start_substeps: >= 1 (EPI only).
+ *   info  : optional; when non-NULL every call is synchronised and info gets
+ *           the worst status and the summed work of all the phi combinations.
+ * The context keeps a workspace of about (2P + M + 6) N doubles for it.
+ * Errors: KP_EINVAL, KP_ENOMEM, KP_EHIP.
+ */
+#define KP_RHS_ALLEN_CAHN 0
+#define KP_RHS_ADR        1
+#define KP_EPI4   0
+#define KP_EPI5   1
+#define KP_SRERK3 2
+
+typedef struct kp_rhs {
+    int32_t kind;
+    int32_t nx, ny;
+    int32_t reserved;
+    double dx, dy;
+    double nu, ax, ay, gamma;
+} kp_rhs;
+
+int kp_integrate(kp_ctx* ctx, const kp_rhs* f, int32_t method, double dt, int32_t nsteps,
+                 int32_t start_substeps, double* u, double tol, int32_t m_max, kp_info* info);
+
 /* Copy the (tau, m) of the accepted substeps of problem i of the last batched
  * call into host arrays of capacity cap; returns the number copied (>= 0) or
  * a KP_E code (KP_ESTATE: no batched call yet; KP_EINVAL: i out of range). */
@@ -336,6 +402,13 @@ const char* kp_last_error(kp_ctx* ctx);
 
 /* Library version, major*10000 + minor*100 + patch. */
 int kp_version(void);
+
+/* Versions of the HIP runtime and driver this library is bound to in the
+ * calling process (hipRuntimeGetVersion, hipDriverGetVersion), for reports:
+ * a process that loads another copy of the runtime first (PyTorch ships one)
+ * binds the library to that copy.  Either pointer may be NULL.
+ * Errors: KP_EHIP. */
+int kp_runtime_version(int32_t* runtime_host, int32_t* driver_host);
 
 #ifdef __cplusplus
 }

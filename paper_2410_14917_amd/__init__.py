@@ -15,8 +15,8 @@ from . import _lib
 from ._lib import (KP_OP_ADR, KP_OP_ALLEN_CAHN, KP_OP_BRUSSELATOR, KpConfig, KpInfo,
                    KpOp)
 
-__all__ = ["Context", "Operator", "phi_combo", "KP_OP_ADR", "KP_OP_ALLEN_CAHN",
-           "KP_OP_BRUSSELATOR"]
+__all__ = ["Context", "Operator", "phi_combo", "runtime_info", "batch_plan", "SolveError",
+           "raise_on_status", "KP_OP_ADR", "KP_OP_ALLEN_CAHN", "KP_OP_BRUSSELATOR"]
 
 
 def _torch():
@@ -58,12 +58,61 @@ class Operator:
         def ptr(t):
             if t is None:
                 return None
-            if t.dtype != _torch().float64 or not t.is_cuda or not t.is_contiguous():
-                raise ValueError("operator fields must be contiguous float64 device tensors")
+            _check_vec("an operator field", t, self.nx * self.ny)
             return ctypes.c_void_p(t.data_ptr())
         return KpOp(self.kind, self.nx, self.ny, int(self.transpose), self.dx, self.dy,
                     self.nu, self.nu2, self.ax, self.ay, self.react, self.brus_a,
                     self.brus_b, ptr(self.field0), ptr(self.field1))
+
+
+STATUS_NAMES = {0: "ok", 1: "not converged", 2: "non-finite data", 3: "aborted (wait limit)"}
+
+
+class SolveError(RuntimeError):
+    """A solve ended with kp_info.status != KP_STATUS_OK."""
+
+    def __init__(self, info):
+        self.info = info
+        super().__init__(f"libkrylov_phi: solve ended with status {info['status']} "
+                         f"({STATUS_NAMES.get(info['status'], '?')}): {info}")
+
+
+def raise_on_status(info):
+    """Raise SolveError unless the kp_info record (as a dict) reports OK."""
+    if info["status"] != 0:
+        raise SolveError(info)
+    return info
+
+
+def _check_vec(name, t, n, device=None):
+    """A caller-supplied output must be a contiguous float64 device vector of
+    n elements (on `device` when given); checked before any launch, since the
+    kernels write n float64 through its pointer."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the inputs on {device}")
+    return t
+
+
+def _b_layout(B, n):
+    """(p, ldb) of a (p+1, N) right-hand-side tensor with unit stride along N."""
+    if B.dim() != 2 or B.shape[1] != n or (n > 1 and B.stride(1) != 1):
+        raise ValueError(f"B must have shape (p+1, {n}) with unit stride along N")
+    # the stride of a single row is arbitrary (torch and numpy may report 1)
+    ldb = B.stride(0) if B.shape[0] > 1 else n
+    if ldb < n:
+        raise ValueError(f"rows of B overlap (row stride {ldb} < {n})")
+    return B.shape[0] - 1, ldb
 
 
 def _stream_handle(stream=None):
@@ -77,13 +126,18 @@ class Context:
 
     def __init__(self, orth="h-gsmgs", basis="f64", max_substeps=0, fixed_m=0,
                  fixed_substeps=0, fallback_delta=0.0, breakdown_eps=0.0, m_init=0,
-                 tau_init=0.0, stream=None):
+                 tau_init=0.0, controller="power", rows_per_wg=0, stream=None):
+        """orth: "h-gsmgs" (default), "h-cwy", "h-ncwy" (Algorithm 4 with the
+        correction of Algorithm 7, 5, 6), "mgs" (Algorithm 1) or "iocgs"
+        (incomplete classical Gram-Schmidt over the previous two vectors);
+        controller: "power" or "pi"; rows_per_wg: grid rows per workgroup of
+        a single call (0: automatic)."""
         self.lib = _lib.load()
         self._stream = stream
         self.cfg = KpConfig(_stream_handle(stream), _lib.ORTH[orth], _lib.BASIS[basis],
                             int(m_init), int(max_substeps), int(fixed_m),
                             int(fixed_substeps), float(fallback_delta), float(breakdown_eps),
-                            float(tau_init))
+                            float(tau_init), _lib.CTRL[controller], int(rows_per_wg))
         h = ctypes.c_void_p()
         _lib.check(self.lib.kp_create(ctypes.byref(h), ctypes.byref(self.cfg)))
         self.h = h
@@ -110,9 +164,7 @@ class Context:
         torch = _torch()
         if B.dtype != torch.float64 or not B.is_cuda:
             raise ValueError("B must be a float64 device tensor of shape (p+1, N)")
-        if B.dim() != 2 or B.shape[1] != n or B.stride(1) != 1:
-            raise ValueError(f"B must have shape (p+1, {n}) with unit stride along N")
-        return B.shape[0] - 1, B.stride(0)
+        return _b_layout(B, n)
 
     def phi_combo(self, op: Operator, B, h: float, tol: float = 1e-8, m_max: int = 64,
                   out=None, info: bool = False):
@@ -122,6 +174,7 @@ class Context:
         p, ldb = self._check_B(B, n)
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=B.device)
+        _check_vec("out", out, n, B.device)
         opc = op.c_struct()
         inf = KpInfo() if info else None
         rc = self.lib.kp_phi_combo(self.h, ctypes.byref(opc), ctypes.c_void_p(B.data_ptr()),
@@ -143,6 +196,10 @@ class Context:
             out = torch.empty(n, dtype=torch.float64, device=B.device)
         if dout is None:
             dout = torch.empty(n, dtype=torch.float64, device=B.device)
+        _check_vec("out", out, n, B.device)
+        _check_vec("dout", dout, n, B.device)
+        if out.data_ptr() == dout.data_ptr():
+            raise ValueError("out and dout must be different tensors")
         opc, dopc = op.c_struct(), dop.c_struct()
         inf = KpInfo() if info else None
         rc = self.lib.kp_phi_combo_tangent(
@@ -163,8 +220,7 @@ class Context:
         torch = _torch()
         n = op.n
         p, ldb = self._check_B(B, n)
-        if g.dtype != torch.float64 or not g.is_cuda or not g.is_contiguous() or g.numel() != n:
-            raise ValueError("g must be a contiguous float64 device vector of N")
+        _check_vec("g", g, n, B.device)
         mask = 0
         for c in coefs:
             mask |= 1 << self.COEFS.index(c)
@@ -200,8 +256,7 @@ class Context:
         op_ = (ctypes.c_void_p * n)()
         for i, (o, B, y) in enumerate(zip(ops, Bs, outs)):
             p, ldb = self._check_B(B, o.n)
-            if y.dtype != torch.float64 or not y.is_cuda or not y.is_contiguous() or y.numel() != o.n:
-                raise ValueError("outs[i] must be a contiguous float64 device vector of N_i")
+            _check_vec(f"outs[{i}]", y, o.n, B.device)
             bp[i], pp[i], lb[i], op_[i] = B.data_ptr(), p, ldb, y.data_ptr()
         inf = (KpInfo * n)() if info else None
         rc = self.lib.kp_phi_combo_batched(self.h, n, opc, bp, pp, lb, hh, float(tol), int(m_max),
@@ -257,6 +312,28 @@ class Context:
         return {"H": H.reshape(m_max, m_max + 1).T, "j": j.value, "beta": beta.value,
                 "breakdown": flags[0], "n_fallback": flags[1], "V": V}
 
+    def integrate(self, rhs, u, dt: float, nsteps: int, method: str = "epi4",
+                  tol: float = 1e-12, m_max: int = 64, start_substeps: int = 4,
+                  info: bool = False):
+        """Advance u (a contiguous float64 device vector of nx*ny, updated in
+        place) by nsteps steps of size dt of an exponential integrator of
+        Section 4.1 ("epi4", "epi5", "srerk3") for u' = f(u); rhs has the
+        fields kind (0 Allen-Cahn, 1 ADR), nx, ny, dx, dy, nu, ax, ay, gamma
+        (e.g. a workloads.Rhs).  Every phi combination is a library call with
+        this context's configuration."""
+        n = int(rhs.nx) * int(rhs.ny)
+        _check_vec("u", u, n)
+        r = _lib.KpRhs(int(rhs.kind), int(rhs.nx), int(rhs.ny), 0, float(rhs.dx), float(rhs.dy),
+                       float(rhs.nu), float(getattr(rhs, "ax", 0.0)),
+                       float(getattr(rhs, "ay", 0.0)), float(getattr(rhs, "gamma", 0.0)))
+        inf = KpInfo() if info else None
+        rc = self.lib.kp_integrate(self.h, ctypes.byref(r), _lib.METHODS[method], float(dt),
+                                   int(nsteps), int(start_substeps), ctypes.c_void_p(u.data_ptr()),
+                                   float(tol), int(m_max),
+                                   ctypes.byref(inf) if inf is not None else None)
+        _lib.check(rc, self.h)
+        return (u, inf.as_dict()) if info else u
+
     def expm_hbar(self, H, m: int, tau: float):
         """exp(tau Hbar) e_1 by the device's Pade routine; H is (m+1) x m."""
         import numpy as np
@@ -272,6 +349,27 @@ def phi_combo(op: Operator, B, h: float, tol: float = 1e-8, m_max: int = 64,
     """One-shot convenience wrapper (creates and frees a Context)."""
     with Context(**ctx_kw) as ctx:
         return ctx.phi_combo(op, B, h, tol=tol, m_max=m_max, info=info)
+
+
+def runtime_info():
+    """The HIP runtime the library is bound to in this process: its version
+    and driver version (from the library), and the paths of every HIP runtime
+    and HSA runtime mapped into the process."""
+    lib = _lib.load()
+    rv, dv = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(lib.kp_runtime_version(ctypes.byref(rv), ctypes.byref(dv)))
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if len(line.split()) >= 6 else ""
+                base = path.rsplit("/", 1)[-1]
+                if base.startswith(("libamdhip64", "libhsa-runtime64")):
+                    paths.add(path)
+    except OSError:
+        pass
+    return {"hip_runtime_version": rv.value, "hip_driver_version": dv.value,
+            "mapped_runtimes": sorted(paths)}
 
 
 def batch_plan(ops, ps, hs, m_max: int = 64, n_wg: int = 256):

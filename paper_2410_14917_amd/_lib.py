@@ -15,19 +15,26 @@ LIB_PATH = os.path.join(HERE, "libkrylov_phi.so")
 # ---- constants (mirror include/krylov_phi.h) --------------------------------
 KP_OK, KP_EINVAL, KP_ENOMEM, KP_EHIP, KP_EUNSUPPORTED, KP_ESTATE = 0, -1, -2, -3, -4, -5
 KP_STATUS_OK, KP_STATUS_NOT_CONVERGED, KP_STATUS_NONFINITE, KP_STATUS_ABORTED = 0, 1, 2, 3
-KP_ORTH_H_GSMGS, KP_ORTH_H_CWY, KP_ORTH_H_NCWY = 0, 1, 2
+KP_ORTH_H_GSMGS, KP_ORTH_H_CWY, KP_ORTH_H_NCWY, KP_ORTH_MGS, KP_ORTH_IOCGS = 0, 1, 2, 3, 4
+KP_CTRL_POWER, KP_CTRL_PI = 0, 1
 KP_OP_ADR, KP_OP_ALLEN_CAHN, KP_OP_BRUSSELATOR = 0, 1, 2
 KP_BASIS_F64, KP_BASIS_F32 = 0, 1
+KP_RHS_ALLEN_CAHN, KP_RHS_ADR = 0, 1
+KP_EPI4, KP_EPI5, KP_SRERK3 = 0, 1, 2
+METHODS = {"epi4": KP_EPI4, "epi5": KP_EPI5, "srerk3": KP_SRERK3}
 KP_MMAX, KP_PMAX = 64, 8
 
-ORTH = {"h-gsmgs": KP_ORTH_H_GSMGS, "h-cwy": KP_ORTH_H_CWY, "h-ncwy": KP_ORTH_H_NCWY}
+ORTH = {"h-gsmgs": KP_ORTH_H_GSMGS, "h-cwy": KP_ORTH_H_CWY, "h-ncwy": KP_ORTH_H_NCWY,
+        "mgs": KP_ORTH_MGS, "iocgs": KP_ORTH_IOCGS}
+CTRL = {"power": KP_CTRL_POWER, "pi": KP_CTRL_PI}
 BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
 
 # Exported symbols (every function declared in the header).
 SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_tangent",
            "kp_phi_combo_backward", "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
-           "kp_strerror", "kp_last_error", "kp_version")
+           "kp_integrate",
+           "kp_strerror", "kp_last_error", "kp_version", "kp_runtime_version")
 
 
 class KpOp(ctypes.Structure):
@@ -44,7 +51,15 @@ class KpConfig(ctypes.Structure):
                 ("basis_dtype", ctypes.c_int32), ("m_init", ctypes.c_int32),
                 ("max_substeps", ctypes.c_int32), ("fixed_m", ctypes.c_int32),
                 ("fixed_substeps", ctypes.c_int32), ("fallback_delta", ctypes.c_double),
-                ("breakdown_eps", ctypes.c_double), ("tau_init", ctypes.c_double)]
+                ("breakdown_eps", ctypes.c_double), ("tau_init", ctypes.c_double),
+                ("controller", ctypes.c_int32), ("rows_per_wg", ctypes.c_int32)]
+
+
+class KpRhs(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("nu", ctypes.c_double), ("ax", ctypes.c_double), ("ay", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
 
 class KpInfo(ctypes.Structure):
@@ -103,11 +118,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_arnoldi_step.argtypes = [P, I32]
     lib.kp_arnoldi_read.argtypes = [P, P, P, P, P, P]
     lib.kp_expm_hbar.argtypes = [P, P, I32, I32, D, P]
+    lib.kp_integrate.argtypes = [P, ctypes.POINTER(KpRhs), I32, D, I32, I32, P, D, I32,
+                                 ctypes.POINTER(KpInfo)]
     lib.kp_strerror.argtypes = [ctypes.c_int]
     lib.kp_strerror.restype = ctypes.c_char_p
     lib.kp_last_error.argtypes = [P]
     lib.kp_last_error.restype = ctypes.c_char_p
     lib.kp_version.argtypes = []
+    lib.kp_runtime_version.argtypes = [P, P]
     for name in SYMBOLS:
         fn = getattr(lib, name)
         if fn.restype is None and name not in ("kp_strerror", "kp_last_error"):

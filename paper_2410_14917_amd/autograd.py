@@ -19,7 +19,7 @@ the tensors.
 """
 from __future__ import annotations
 
-from . import Context, Operator
+from . import Context, Operator, raise_on_status
 
 COEFS = ("nu", "ax", "ay", "react")
 
@@ -58,7 +58,12 @@ def _fn():
             vals = {name: float(t) for name, t in zip(COEFS, (nu, ax, ay, react))
                     if t is not None}
             opn = _with(op, **vals)
-            y = _context(ctx_kw).phi_combo(opn, B.contiguous(), h, tol=tol, m_max=m_max)
+            # the solve's status is checked (a call that did not converge,
+            # met non-finite data or was aborted raises SolveError rather
+            # than returning a wrong or unwritten y)
+            y, info = _context(ctx_kw).phi_combo(opn, B.contiguous(), h, tol=tol, m_max=m_max,
+                                                 info=True)
+            raise_on_status(info)
             ctx.save_for_backward(B)
             ctx.op, ctx.h, ctx.tol, ctx.m_max, ctx.ctx_kw = opn, h, tol, m_max, ctx_kw
             return y
@@ -68,9 +73,10 @@ def _fn():
             (B,) = ctx.saved_tensors
             want_B = ctx.needs_input_grad[0]
             coefs = [name for name, need in zip(COEFS, ctx.needs_input_grad[1:5]) if need]
-            gB, gc = _context(ctx.ctx_kw).phi_combo_backward(
+            gB, gc, info = _context(ctx.ctx_kw).phi_combo_backward(
                 ctx.op, B.contiguous(), ctx.h, g.contiguous(), tol=ctx.tol, m_max=ctx.m_max,
-                want_B=want_B, coefs=coefs)
+                want_B=want_B, coefs=coefs, info=True)
+            raise_on_status(info)   # the worst status of the backward's solves
             grads = [gc[COEFS.index(name)].reshape(()) if name in coefs else None
                      for name in COEFS]
             return (gB, *grads, None, None, None, None, None)

@@ -12,6 +12,8 @@ SRC = os.path.join(HERE, "csrc", "krylov_phi.hip")
 OUT = os.path.join(HERE, "libkrylov_phi.so")
 CLIENT_SRC = os.path.join(ROOT, "tests", "c_abi_client.cpp")
 CLIENT = os.path.join(ROOT, "tests", "c_abi_client")
+RUNNER_SRC = os.path.join(HERE, "kp_run.cpp")
+RUNNER = os.path.join(HERE, "kp_run")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -30,7 +32,26 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     os.replace(tmp, OUT)
     build_client(verbose)
+    build_runner(verbose)
     return OUT
+
+
+def build_runner(verbose: bool = False) -> str:
+    """The native runner (kp_run.cpp: the C ABI and the system HIP runtime,
+    for profiling a process that maps one runtime), next to the library."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = RUNNER + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I" + os.path.join(ROOT, "include"), RUNNER_SRC, "-o", tmp, "-L" + HERE,
+           "-lkrylov_phi", "-Wl,-rpath,$ORIGIN"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("building kp_run failed:\n" + res.stdout + res.stderr)
+    if verbose:
+        print(" ".join(cmd))
+    os.replace(tmp, RUNNER)
+    return RUNNER
 
 
 def build_client(verbose: bool = False) -> str:

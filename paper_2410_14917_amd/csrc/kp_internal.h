@@ -60,7 +60,19 @@ enum Phase : int {
   PH_COMBINE = 4,
   PH_FINISH = 5,
   PH_DONE = 6,
+  // the processes with one reduction per inner product (Algorithm 1) or per
+  // window (ioCGS): a plain matvec with its first products, then projection
+  // phases, each ending in a grid-wide reduction
+  PH_MVEC = 7,     // w = Atilde x_j and the first inner products
+  PH_PROJ = 8,     // w -= h_i x_i for the pending columns, then x_i' . w or ||w||^2
 };
+
+// Orthogonalisations that take one grid-wide reduction per inner product
+// (MGS) or per window (ioCGS) run the PH_MVEC / PH_PROJ phases; the hybrid
+// forms of Algorithm 4 run PH_STEP / PH_CLOSE.
+__host__ __device__ inline bool orth_multi_sync(int orth) {
+  return orth == KP_ORTH_MGS || orth == KP_ORTH_IOCGS;
+}
 
 constexpr int kFlagStride = 16;           // unsigned per workgroup flag (64 B)
 
@@ -75,6 +87,7 @@ struct Pub {
   int status;
   int pad_[2];
   double inv_mu;
+  double xscale;            // MGS / ioCGS: unit scale of the column the next matvec multiplies
   double coef[kMMax + 2];   // coefficients of the pending update / of the combine
 };
 
@@ -91,6 +104,7 @@ struct State {
   int m_last;
   int pad_[3];
   double t, tau, beta, mu, err_max, omega, err, last_nrm2;
+  double omega_prev;  // normalised error of the last accepted substep (PI control)
   double sigma[kMMax + 2];   // unit scale of stored basis column i
   double gamma[kMMax + 2];   // divisor applied to column i+1 when it was written
   double wn2[kMMax + 2];     // ||A u_j||^2 of step j
@@ -139,6 +153,7 @@ struct Args {
   double cx, cy, cx2, cy2, adx, ady, react, ba, bb;
   double dcx, dcy, dadx, dady, dreact;   // tangent mode: the direction dA
   int orth, fixed_m, fixed_substeps, max_substeps, m_max;
+  int controller;     // KP_CTRL_POWER or KP_CTRL_PI
   int m0;             // Krylov dimension of the first substep
   double tau0;        // length of the first substep
   int stop_j;         // pause when this many steps are completed (INT_MAX: never)
@@ -253,20 +268,23 @@ struct Ctl {
   int m_eff;    // Krylov dimension available (small exponential, combine)
   int last;     // the accepted substep ends at h
   int status;
+  int i;        // PH_PROJ: column of the next inner product (j + 1: the norm)
 };
 
 __device__ inline unsigned ctl_pack(const Ctl& c) {
-  return (unsigned)c.phase | ((unsigned)c.j << 3) | ((unsigned)c.upd << 10) |
-         ((unsigned)c.m_eff << 11) | ((unsigned)c.last << 18) | ((unsigned)c.status << 19);
+  return (unsigned)c.phase | ((unsigned)c.j << 4) | ((unsigned)c.upd << 11) |
+         ((unsigned)c.m_eff << 12) | ((unsigned)c.last << 19) | ((unsigned)c.status << 20) |
+         ((unsigned)c.i << 22);
 }
 __device__ inline Ctl ctl_unpack(unsigned w) {
   Ctl c;
-  c.phase = (int)(w & 7u);
-  c.j = (int)((w >> 3) & 127u);
-  c.upd = (int)((w >> 10) & 1u);
-  c.m_eff = (int)((w >> 11) & 127u);
-  c.last = (int)((w >> 18) & 1u);
-  c.status = (int)((w >> 19) & 3u);
+  c.phase = (int)(w & 15u);
+  c.j = (int)((w >> 4) & 127u);
+  c.upd = (int)((w >> 11) & 1u);
+  c.m_eff = (int)((w >> 12) & 127u);
+  c.last = (int)((w >> 19) & 1u);
+  c.status = (int)((w >> 20) & 3u);
+  c.i = (int)((w >> 22) & 127u);
   return c;
 }
 

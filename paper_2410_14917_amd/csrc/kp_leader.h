@@ -137,6 +137,11 @@ __device__ __attribute__((always_inline)) inline void gather_step_partials(const
   __syncthreads();
 }
 
+// First phase of an Arnoldi step for the configured process.
+__device__ inline int step_phase(const Args& a) {
+  return orth_multi_sync(a.orth) ? (int)PH_MVEC : (int)PH_STEP;
+}
+
 // ---- stage leader: balance mu, augmented tail, first phase -----------------
 __device__ __attribute__((always_inline)) inline void leader_stage(const Args& a, double* red, Ctl& nx) {
   double m0 = 0.0, m1 = 0.0;
@@ -170,7 +175,7 @@ __device__ __attribute__((always_inline)) inline void leader_stage(const Args& a
     } else {
       nx.j = 0;
       nx.upd = 0;
-      nx.phase = (int)PH_STEP;
+      nx.phase = step_phase(a);
     }
   }
 }
@@ -434,6 +439,111 @@ __device__ __attribute__((always_inline)) inline void leader_close(const Args& a
   nx.phase = (int)((L.breakdown || j >= L.m_target) ? PH_EXPM : PH_STEP);
 }
 
+// ---- the leader of the processes with one reduction per inner product -----
+// (Algorithm 1, MGS) or per window (ioCGS, Section 2.3.1).  Column i stores
+// x_i with v_i = sigma_i x_i.  During step jj column jj+1 holds w / r with
+// r = sigma_0 at jj = 0 (the matvec multiplied u = x_0 itself) and r = 1
+// after (it multiplied v_jj), so an inner product v_i . w is
+// sigma_i r (x_i . column), the projection w -= h v_i adds -h sigma_i / r x_i
+// to the column, and ||w|| = r ||column||.
+
+// After the matvec of step jj: tv = [x.x, x.w, w.w, x_acol.w].
+__device__ inline void leader_mvec(const Args& a, int jj, const double* tv, LeadLds& L, Ctl& nx) {
+  if (kp_tid() != 0) return;
+  State* st = a.st;
+  Pub* pb = a.pub;
+  const double xx = tv[0], xw = tv[1], ww = tv[2], aw = tv[3];
+  if (!isfinite(xx) || !isfinite(xw) || !isfinite(ww) || !isfinite(aw)) {
+    nx.status = (int)KP_STATUS_NONFINITE;
+    nx.phase = (int)PH_FINISH;
+    return;
+  }
+  if (jj == 0) {
+    const double beta = sqrt(xx);
+    if (beta == 0.0) {                       // zero start vector: the result is zero
+      st->zero = 1;
+      st->beta = 0.0;
+      nx.phase = (int)PH_FINISH;
+      return;
+    }
+    st->beta = beta;
+    L.sigma[0] = 1.0 / beta;
+    st->sigma[0] = 1.0 / beta;
+  }
+  const double sj = L.sigma[jj];
+  const double r = jj == 0 ? sj : 1.0;
+  L.wn2[jj] = r * r * ww;                    // ||A v_jj||^2 (breakdown test)
+  st->wn2[jj] = L.wn2[jj];
+  double* Hc = st->H + (int64_t)jj * kLdh;
+  if (a.orth == KP_ORTH_MGS) {
+    // first inner product of Algorithm 1: h_{1,j} = v_1 . w
+    const double s0 = L.sigma[0];
+    const double h = s0 * r * (jj == 0 ? xw : aw);
+    Hc[0] = h;
+    cstore(&pb->coef[0], -h * s0 / r);
+    nx.i = 1;                                // jj == 0: 1 = jj + 1, the norm
+  } else {
+    // ioCGS: both products of the window from the same w
+    const double h = sj * r * xw;
+    Hc[jj] = h;
+    cstore(&pb->coef[jj], -h * sj / r);
+    if (jj >= 1) {
+      const double sa = L.sigma[jj - 1];
+      const double ha = sa * r * aw;
+      Hc[jj - 1] = ha;
+      cstore(&pb->coef[jj - 1], -ha * sa / r);
+    }
+    nx.i = jj + 1;
+  }
+  nx.phase = (int)PH_PROJ;
+}
+
+// After projection phase i of step jj (s: the reduced slot 0).  i <= jj: the
+// MGS inner product with v_i; i = jj + 1: the norm of the projected vector,
+// which gives H_{j+1,j} and the unit scale of column jj+1.
+__device__ inline void leader_proj(const Args& a, int jj, int i, double s, LeadLds& L, Ctl& nx) {
+  if (kp_tid() != 0) return;
+  State* st = a.st;
+  Pub* pb = a.pub;
+  if (!isfinite(s)) {
+    nx.status = (int)KP_STATUS_NONFINITE;
+    nx.phase = (int)PH_FINISH;
+    return;
+  }
+  const double r = jj == 0 ? L.sigma[0] : 1.0;
+  double* Hc = st->H + (int64_t)jj * kLdh;
+  if (i <= jj) {
+    const double si = L.sigma[i];
+    const double h = si * r * s;
+    Hc[i] = h;
+    cstore(&pb->coef[i], -h * si / r);
+    nx.i = i + 1;
+    nx.phase = (int)PH_PROJ;
+    return;
+  }
+  const double nw = sqrt(s);                 // || column jj+1 ||
+  const double nrm = r * nw;                 // || projected w ||
+  const int j = jj + 1;
+  st->arnoldi_steps = ++L.arnoldi_steps;
+  st->last_nrm2 = s;
+  nx.j = j;
+  nx.m_eff = j;
+  nx.i = 0;
+  nx.upd = 0;
+  if (!(nrm > a.eps_bd * sqrt(L.wn2[jj]))) {  // lucky breakdown (also w = 0)
+    Hc[j] = 0.0;
+    st->breakdown = 1;
+    L.breakdown = 1;
+    nx.phase = (int)PH_EXPM;
+    return;
+  }
+  Hc[j] = nrm;
+  L.sigma[j] = 1.0 / nw;
+  st->sigma[j] = 1.0 / nw;
+  cstore(&pb->xscale, 1.0 / nw);             // the next matvec multiplies v_j
+  nx.phase = (int)(j >= L.m_target ? PH_EXPM : PH_MVEC);
+}
+
 // ---- small exponential + substep controller (workgroup 0) -------------------
 // The controller is this library's own (the paper defers it to KIOPS without
 // printing the formulas): omega = err h / (tol beta tau), accept iff
@@ -446,6 +556,16 @@ __device__ inline double tau_factor(double omega, int m) {
   if (omega == 0.0) return 4.0;
   const int q = (m + 3) / 4;
   return fmin(4.0, fmax(0.2, 0.9 * pow(omega, -1.0 / (double)(q + 1))));
+}
+
+// The proportional-integral law (KP_CTRL_PI) after an accepted substep whose
+// predecessor was accepted with error omega_prev > 0: the integral gain 0.7
+// and the proportional gain 0.4 (per q + 1) of Gustafsson's PI controller.
+__device__ inline double tau_factor_pi(double omega, double omega_prev, int m) {
+  if (omega == 0.0) return 4.0;
+  const int q = (m + 3) / 4;
+  const double f = 0.9 * pow(omega, -0.7 / (double)(q + 1)) * pow(omega_prev, 0.4 / (double)(q + 1));
+  return fmin(4.0, fmax(0.2, f));
 }
 
 __device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, double* lds, LeadLds& L,
@@ -509,7 +629,7 @@ __device__ __attribute__((always_inline)) inline void expm_phase(const Args& a, 
       L.m_target = st->m_cur;
       st->tau = tau;
       nx.upd = 0;
-      nx.phase = (int)PH_STEP;
+      nx.phase = step_phase(a);
     }
   } else {
     if (kp_tid() == 0) {
@@ -544,7 +664,10 @@ __device__ __attribute__((always_inline)) inline void leader_combine(const Args&
   }
   double tn = tau;
   if (!fixed) {
-    tn = tau * tau_factor(st->omega, m);
+    tn = tau * ((a.controller == KP_CTRL_PI && st->omega_prev > 0.0)
+                    ? tau_factor_pi(st->omega, st->omega_prev, m)
+                    : tau_factor(st->omega, m));
+    st->omega_prev = st->omega;
     if (st->substeps >= a.max_substeps) {
       nx.status = (int)KP_STATUS_NOT_CONVERGED;
       nx.phase = (int)PH_FINISH;
@@ -559,7 +682,7 @@ __device__ __attribute__((always_inline)) inline void leader_combine(const Args&
   L.m_target = st->m_target;
   nx.j = 0;
   nx.upd = 0;
-  nx.phase = (int)PH_STEP;
+  nx.phase = step_phase(a);
 }
 
 }  // namespace kp

@@ -769,6 +769,195 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
   if (wg_rank(a) == 0) tail_combine_cols<TB, double>(a, V, m, coef, -1, 0.0, a.u, !last);
 }
 
+// ---- processes with one reduction per inner product (Algorithm 1) or per
+// window (ioCGS, Section 2.3.1) ----------------------------------------------
+//
+// Step jj is a matvec phase (PH_MVEC) followed by projection phases (PH_PROJ),
+// each ending in a grid-wide reduction of a few partial sums (the counted
+// buffer).  Stored columns carry unit scales as in the hybrid path (x_i =
+// column i, v_i = sigma_i x_i).  The matvec multiplies the unit vector
+// v_jj = sigma_jj x_jj (sigma_jj published as Pub::xscale; at jj = 0 the
+// state vector u itself, whose norm is not known yet), so every stored column
+// has the size of A v and none grows with the step; the new column jj+1 is
+// projected in place and the leader folds the scales into the coefficients.
+constexpr int kMvSlots = 4;   // x.x, x.w, w.w, x_a.w
+
+// Tail rows of the matvec of step jj (lane 0 of workgroup 0: at most kPMax
+// entries): w_tail = K (xs x_tail), stored (x_tail too at the first step), and
+// their share of the four products.
+template <typename TB>
+__device__ inline void tail_mvec(const Args& a, int jj, const Src<TB>& x, TB* V, int acol,
+                                 double xs, double* sacc) {
+  if (kp_tid() != 0) return;
+  const int64_t T0 = a.tail_off, ld = a.ld;
+  TB* xcol = V + (int64_t)jj * ld;
+  TB* wcol = V + (int64_t)(jj + 1) * ld;
+  double xx = 0.0, xw = 0.0, ww = 0.0, aw = 0.0;
+  for (int k = 0; k < a.p; ++k) {
+    const double xk = x(T0 + k);
+    const double wk = rnd<TB>(tail_shift_in(a, k) ? xs * x(T0 + k + 1) : 0.0);
+    wcol[T0 + k] = (TB)wk;
+    if (jj == 0) xcol[T0 + k] = (TB)xk;
+    xx += xk * xk;
+    xw += xk * wk;
+    ww += wk * wk;
+    if (acol >= 0) aw += (double)V[(int64_t)acol * ld + T0 + k] * wk;
+  }
+  sacc[0] += xx;
+  sacc[1] += xw;
+  sacc[2] += ww;
+  sacc[3] += aw;
+}
+
+// Matvec of step jj: w = Atilde (s x_jj) into column jj+1, s = Pub::xscale
+// (1 at jj = 0, where x_0 = u is stored into column 0), and the partial sums
+// x.x, x.w, w.w and, when acol >= 0, x_acol . w, written to this workgroup's
+// row of the counted buffer.  sacc: kWaves * kMvSlots doubles of LDS; hl: the
+// LDS halo copy.
+template <typename TB, bool HL>
+__device__ __attribute__((always_inline)) inline void mvec_pass(const Args& a, int jj, int acol,
+                                                                double* sacc, double* hl) {
+  TB* V = reinterpret_cast<TB*>(a.V);
+  const int64_t ld = a.ld;
+  const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
+  const Rows o = own_rows(a);
+  for (int k = kp_tid(); k < kWaves * kMvSlots; k += kThreads) sacc[k] = 0.0;
+  if (HL) stage_halo<TB>(a, o, hl);
+  const double inv_mu = cload(&a.pub->inv_mu);
+  const double xs = jj == 0 ? 1.0 : cload(&a.pub->xscale);
+  __syncthreads();
+  TB* xcol = V + (int64_t)jj * ld;
+  TB* wcol = V + (int64_t)(jj + 1) * ld;
+  const TB* acp = V + (int64_t)(acol >= 0 ? acol : 0) * ld;
+  const Src<TB> x{xcol, a.u, jj == 0};
+  double sxx = 0.0, sxw = 0.0, sww = 0.0, saw = 0.0;
+  const int ns = num_segs(a);
+  for (int si = 0; si < ns; ++si) {
+    const Seg sg = seg_at(a, o, si);
+    const int64_t pend = (sg.end + 1) >> 1;
+    const int toff = (a.tangent && sg.plane == 1) ? a.pb : 0;
+    double tc[kPMax];
+#pragma unroll
+    for (int c = 0; c < kPMax; ++c)
+      tc[c] = (c < a.pb) ? rnd<TB>(cload(a.tx + toff + c)) * inv_mu : 0.0;
+    for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
+      const int64_t t0 = 2 * q0;
+      uint32_t lo[kR];
+      bool ok[kR];
+      tile_pairs(q0, pend, lo, ok);
+      double2 xv[kR], wv2[kR], av[kR];
+      const TB* ac = uniform_ptr(acp + t0);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        xv[r] = x.pair(t0 + lo[r]);
+        av[r] = (acol >= 0) ? load_at(ac, lo[r] * (uint32_t)sizeof(TB)) : make_double2(0.0, 0.0);
+      }
+      aug_tile<TB, HL>(a, o, sg, x, hl, t0, lo, tc, wv2);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        wv2[r].x = rnd<TB>(xs * wv2[r].x);
+        wv2[r].y = rnd<TB>(xs * wv2[r].y);
+        if (ok[r]) {
+          Pair<TB>::store(wcol + t0 + lo[r], wv2[r].x, wv2[r].y);
+          if (jj == 0) Pair<TB>::store(xcol + t0 + lo[r], xv[r].x, xv[r].y);
+        } else {
+          xv[r] = make_double2(0.0, 0.0);
+          wv2[r] = make_double2(0.0, 0.0);
+        }
+        sxx += xv[r].x * xv[r].x + xv[r].y * xv[r].y;
+        sxw += xv[r].x * wv2[r].x + xv[r].y * wv2[r].y;
+        sww += wv2[r].x * wv2[r].x + wv2[r].y * wv2[r].y;
+        saw += av[r].x * wv2[r].x + av[r].y * wv2[r].y;
+      }
+    }
+  }
+  sxx = wave_sum(sxx);
+  sxw = wave_sum(sxw);
+  sww = wave_sum(sww);
+  saw = wave_sum(saw);
+  if (lane == 0) {
+    sacc[wv * kMvSlots + 0] = sxx;
+    sacc[wv * kMvSlots + 1] = sxw;
+    sacc[wv * kMvSlots + 2] = sww;
+    sacc[wv * kMvSlots + 3] = saw;
+  }
+  if (wg_rank(a) == 0) tail_mvec<TB>(a, jj, x, V, acol, xs, sacc);
+  __syncthreads();
+  if (kp_tid() < kMvSlots) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += sacc[w * kMvSlots + kp_tid()];
+    cstore(a.part + (int64_t)wg_rank(a) * kKStride + kp_tid(), s);
+  }
+}
+
+// Projection phase of step jj: column jj+1 (w) += sum_{c = ca..cb} coef[c]
+// x_c in place, then the partial sum x_dcol . w (dcol >= 0) or, with
+// want_norm, ||w||^2, in slot 0 of this workgroup's row of the counted
+// buffer.  With want_norm the result is the next vector the matvec
+// multiplies: its halo rows and tail are published.
+template <typename TB>
+__device__ __attribute__((always_inline)) inline void proj_pass(const Args& a, int jj, int ca, int cb,
+                                                                const double* coef, int dcol,
+                                                                bool want_norm, double* red) {
+  TB* V = reinterpret_cast<TB*>(a.V);
+  const int64_t ld = a.ld;
+  TB* wcol = V + (int64_t)(jj + 1) * ld;
+  const TB* dcp = V + (int64_t)(dcol >= 0 ? dcol : 0) * ld;
+  const Rows o = own_rows(a);
+  double ss = 0.0;
+  const int ns = num_segs(a);
+  for (int si = 0; si < ns; ++si) {
+    const Seg sg = seg_at(a, o, si);
+    const int64_t pend = (sg.end + 1) >> 1;
+    for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
+      const int64_t t0 = 2 * q0;
+      uint32_t lo[kR];
+      bool ok[kR];
+      tile_pairs(q0, pend, lo, ok);
+      double2 acc[kR], dv[kR];
+      const TB* dc = uniform_ptr(dcp + t0);
+      const TB* wc = uniform_ptr(wcol + t0);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        acc[r] = load_at(wc, lo[r] * (uint32_t)sizeof(TB));
+        dv[r] = (dcol >= 0) ? load_at(dc, lo[r] * (uint32_t)sizeof(TB)) : make_double2(0.0, 0.0);
+      }
+      for (int c = ca; c <= cb; ++c) axpy_cols<TB, 1>(V, ld, t0, c, 1, coef, lo, acc);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
+        if (ok[r]) {
+          Pair<TB>::store(wcol + t0 + lo[r], y0, y1);
+          if (want_norm) {
+            ss += y0 * y0 + y1 * y1;
+            publish_pair(a, sg, t0 + lo[r], y0, y1);
+          } else {
+            ss += dv[r].x * y0 + dv[r].y * y1;
+          }
+        }
+      }
+    }
+  }
+  if (wg_rank(a) == 0 && kp_tid() == 0) {
+    // the tail (at most kPMax entries), in the order of the rows above
+    const int64_t T0 = a.tail_off;
+    for (int k = 0; k < a.p; ++k) {
+      double y = (double)wcol[T0 + k];
+      for (int c = ca; c <= cb; ++c) y += cload(coef + c) * (double)V[(int64_t)c * ld + T0 + k];
+      y = rnd<TB>(y);
+      wcol[T0 + k] = (TB)y;
+      if (want_norm) {
+        cstore(a.tx + k, y);
+        ss += y * y;
+      } else {
+        ss += (double)dcp[T0 + k] * y;
+      }
+    }
+  }
+  ss = block_sum(ss, red);
+  if (kp_tid() == 0) cstore(a.part + (int64_t)wg_rank(a) * kKStride, ss);
+}
+
 // ---- finish: out = u_top (or NaN when the input was not finite) -------------
 __device__ __attribute__((always_inline)) inline void finish_pass(const Args& a, bool nonfinite) {
   const Rows o = own_rows(a);

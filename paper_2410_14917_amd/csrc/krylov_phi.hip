@@ -101,6 +101,23 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     case PH_CLOSE:
       update_pass<TB>(a, c.j - 1, a.pub->coef, red, true);
       break;
+    case PH_MVEC: {
+      // MGS multiplies and takes v_1 . w; ioCGS takes v_{j-1} . w and v_j . w
+      const int acol = c.j == 0 ? -1 : (a.orth == KP_ORTH_MGS ? 0 : c.j - 1);
+      if (a.halo_lds)
+        mvec_pass<TB, true>(a, c.j, acol, sacc, hl);
+      else
+        mvec_pass<TB, false>(a, c.j, acol, sacc, hl);
+      break;
+    }
+    case PH_PROJ:
+      // MGS: subtract the projection on v_{i-1}, then v_i . w (or the norm);
+      // ioCGS: subtract both projections of the window, then the norm
+      if (a.orth == KP_ORTH_MGS)
+        proj_pass<TB>(a, c.j, c.i - 1, c.i - 1, a.pub->coef, c.i <= c.j ? c.i : -1, c.i > c.j, red);
+      else
+        proj_pass<TB>(a, c.j, max(0, c.j - 1), c.j, a.pub->coef, -1, true, red);
+      break;
     case PH_COMBINE:
       combine_pass<TB>(a, c.m_eff, a.pub->coef, c.last != 0);
       break;
@@ -138,6 +155,14 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     case PH_CLOSE:
       reduce_partials(a, 1, tv, grp);
       leader_close(a, tv[0], L, nxt);
+      break;
+    case PH_MVEC:
+      reduce_partials(a, kMvSlots, tv, grp);
+      leader_mvec(a, c.j, tv, L, nxt);
+      break;
+    case PH_PROJ:
+      reduce_partials(a, 1, tv, grp);
+      leader_proj(a, c.j, c.i, tv[0], L, nxt);
       break;
     case PH_EXPM:
       expm_phase(a, lds, L, nxt);
@@ -178,7 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
     __syncthreads();
     if (!ok || cur.phase == PH_DONE) break;
     if (arnoldi_only &&
-        (cur.phase >= PH_EXPM || (cur.phase == PH_STEP && cur.j >= a.stop_j)))
+        (cur.phase == PH_EXPM || cur.phase == PH_COMBINE || cur.phase == PH_FINISH ||
+         ((cur.phase == PH_STEP || cur.phase == PH_MVEC) && cur.j >= a.stop_j)))
       break;
     ++k;
     run_phase<TB>(a, lds, lead, cur, nxt, ok, k);
@@ -212,6 +238,7 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   pb->last = 0;
   pb->status = KP_STATUS_OK;
   pb->inv_mu = 1.0;
+  pb->xscale = 1.0;
   st->m_target = m_target;
   st->m_cur = m_target;
   st->breakdown = 0;
@@ -223,7 +250,7 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   st->tau = a.tau0;
   st->beta = 0.0;
   st->mu = 1.0;
-  st->err_max = st->omega = st->err = st->last_nrm2 = 0.0;
+  st->err_max = st->omega = st->err = st->last_nrm2 = st->omega_prev = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
@@ -462,6 +489,122 @@ __global__ __launch_bounds__(256) void k_zero(double* x, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) x[e] = 0.0;
 }
 
+// ---- exponential integrators (Section 4.1): right-hand side and remainders --
+// One thread per grid point of an nx x ny periodic grid; the linear part is
+// nu Lap v - ax Dx v - ay Dy v with the operators' second-order differences.
+
+struct RhsK {
+  int kind, nx, ny;
+  double cx, cy;      // nu / dx^2, nu / dy^2
+  double adx, ady;    // ax / (2 dx), ay / (2 dy)
+  double gamma;
+};
+
+struct Nbr {
+  int64_t e, ie, iw, in, is;
+};
+
+__device__ inline Nbr nbr_at(const RhsK& r, int64_t e) {
+  const int iy = (int)(e / r.nx), ix = (int)(e - (int64_t)iy * r.nx);
+  Nbr b;
+  b.e = e;
+  b.ie = (int64_t)iy * r.nx + (ix + 1 == r.nx ? 0 : ix + 1);
+  b.iw = (int64_t)iy * r.nx + (ix == 0 ? r.nx - 1 : ix - 1);
+  b.in = (int64_t)(iy + 1 == r.ny ? 0 : iy + 1) * r.nx + ix;
+  b.is = (int64_t)(iy == 0 ? r.ny - 1 : iy - 1) * r.nx + ix;
+  return b;
+}
+
+// (nu Lap - ax Dx - ay Dy) of the grid function d(.) at b.e
+template <typename F>
+__device__ inline double lin_at(const RhsK& r, const Nbr& b, F d) {
+  const double c = d(b.e), ve = d(b.ie), vw = d(b.iw), vn = d(b.in), vs = d(b.is);
+  return r.cx * (ve + vw - 2.0 * c) + r.cy * (vn + vs - 2.0 * c) -
+         (r.adx * (ve - vw) + r.ady * (vn - vs));
+}
+
+// The nonlinear term and its derivative at a point value x.
+__device__ inline double nl_term(const RhsK& r, double x) {
+  return r.kind == KP_RHS_ALLEN_CAHN ? x - x * x * x : r.gamma * x * (x - 0.5) * (1.0 - x);
+}
+__device__ inline double nl_deriv(const RhsK& r, double x) {
+  return r.kind == KP_RHS_ALLEN_CAHN ? 1.0 - 3.0 * x * x : r.gamma * (-3.0 * x * x + 3.0 * x - 0.5);
+}
+
+// f = f(u); jd (when non-null) = the Jacobian's diagonal field at u (the
+// ADR kind's KP_OP_ADR field); B (when non-null) = [0, f] (N x 2, ld ldb).
+__global__ __launch_bounds__(256) void k_rhs(RhsK r, const double* u, double* f, double* jd,
+                                             double* B, int64_t ldb) {
+  const int64_t n = (int64_t)r.nx * r.ny;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const Nbr b = nbr_at(r, e);
+  const double x = u[e];
+  const double v = lin_at(r, b, [&](int64_t i) { return u[i]; }) + nl_term(r, x);
+  f[e] = v;
+  if (jd) jd[e] = nl_deriv(r, x);
+  if (B) {
+    B[e] = 0.0;
+    B[ldb + e] = v;
+  }
+}
+
+// The remainder R(w) = f(w) - f(u_n) - J_n (w - u_n) at b.e.
+__device__ inline double remainder_at(const RhsK& r, const Nbr& b, const double* un,
+                                      const double* fn, const double* w, const double* fw) {
+  const auto d = [&](int64_t i) { return w[i] - un[i]; };
+  const double jd = lin_at(r, b, d) + nl_deriv(r, un[b.e]) * d(b.e);
+  return fw[b.e] - fn[b.e] - jd;
+}
+
+// EPI columns of step n: B = [0, f_n, b_2, .., b_M] with
+// b_m = sum_i alpha_{m,i} R(u_{n-i}) / h^{m-1} (v_m = h sum_i alpha_{m,i} R_i,
+// b_m = v_m / h^m).  u[k], f[k] = u_{n-k}, f(u_{n-k}).
+struct EpiK {
+  const double* u[4];
+  const double* f[4];
+  double alpha[4][3];   // alpha[m-1][i-1]
+  double hinv[4];       // hinv[m-1] = 1 / h^{m-1}
+  int M, P;
+};
+
+__global__ __launch_bounds__(256) void k_epi_cols(RhsK r, EpiK q, double* B, int64_t ldb) {
+  const int64_t n = (int64_t)r.nx * r.ny;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const Nbr b = nbr_at(r, e);
+  double R[3] = {0.0, 0.0, 0.0};
+  for (int i = 1; i <= q.P; ++i) R[i - 1] = remainder_at(r, b, q.u[0], q.f[0], q.u[i], q.f[i]);
+  B[e] = 0.0;
+  B[ldb + e] = q.f[0][e];
+  for (int m = 2; m <= q.M; ++m) {
+    double s = 0.0;
+    for (int i = 1; i <= q.P; ++i) s += q.alpha[m - 1][i - 1] * R[i - 1];
+    B[(int64_t)m * ldb + e] = s * q.hinv[m - 1];
+  }
+}
+
+// SRERK3 second stage: B = [0, f_n, 0, c3 R(z)] with c3 = 32/9 / h^2.
+__global__ __launch_bounds__(256) void k_srerk_cols(RhsK r, const double* un, const double* fn,
+                                                    const double* z, const double* fz, double c3,
+                                                    double* B, int64_t ldb) {
+  const int64_t n = (int64_t)r.nx * r.ny;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const Nbr b = nbr_at(r, e);
+  B[e] = 0.0;
+  B[ldb + e] = fn[e];
+  B[2 * ldb + e] = 0.0;
+  B[3 * ldb + e] = c3 * remainder_at(r, b, un, fn, z, fz);
+}
+
+// out = a + y.
+__global__ __launch_bounds__(256) void k_axpy(double* out, const double* a, const double* y,
+                                              int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) out[e] = a[e] + y[e];
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -503,11 +646,14 @@ struct kp_ctx {
   double* tx = nullptr;
   double* aux = nullptr;           // backward: [0...0 g] matrix, tangent outputs, dot partials
   size_t aux_bytes = 0;
+  double* integ = nullptr;         // integrators: state and right-hand-side history, columns
+  size_t integ_bytes = 0;
   int occ[2] = {-1, -1};
   Args last{};
   int have_begin = 0;
   int arn_target = 0;
   BatchCache* batch = nullptr;   // plan, workspace and graph of the last batched call
+  State* st_last = nullptr;      // State of the last single call
   char err[512] = {0};
 };
 
@@ -525,7 +671,9 @@ int hip_fail(kp_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 int check_config(const kp_config* c) {
-  if (c->orth < 0 || c->orth > KP_ORTH_H_NCWY) return KP_EINVAL;
+  if (c->orth < 0 || c->orth > KP_ORTH_IOCGS) return KP_EINVAL;
+  if (c->controller != KP_CTRL_POWER && c->controller != KP_CTRL_PI) return KP_EINVAL;
+  if (c->rows_per_wg < 0) return KP_EINVAL;
   if (c->basis_dtype != KP_BASIS_F64 && c->basis_dtype != KP_BASIS_F32) return KP_EINVAL;
   if (c->m_init < 0 || c->m_init > KP_MMAX) return KP_EINVAL;
   if (!std::isfinite(c->tau_init) || c->tau_init < 0.0) return KP_EINVAL;
@@ -610,6 +758,7 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.ba = A->brus_a;
   r.bb = A->brus_b;
   r.orth = cfg.orth;
+  r.controller = cfg.controller;
   r.fixed_m = cfg.fixed_m;
   r.fixed_substeps = cfg.fixed_m > 0 ? cfg.fixed_substeps : 0;
   r.max_substeps = cfg.max_substeps > 0 ? cfg.max_substeps : 2000;
@@ -678,12 +827,14 @@ int grow(kp_ctx* ctx, void** p, size_t* have, size_t need) {
 }
 
 // Grid geometry: workgroup b owns rows [b*rows, (b+1)*rows) of every plane.
-// At least one full sub-tile (kThreads * kR pairs) of elements per workgroup,
-// at most one workgroup per co-resident slot; an even row count when nx is
-// odd keeps every segment start even (pair alignment).
-void geometry(int ncu_slots, Args* a) {
+// At least one full sub-tile (kThreads * kR pairs) of elements per workgroup
+// (or the configured rows_per_wg), at most one workgroup per co-resident slot;
+// an even row count when nx is odd keeps every segment start even (pair
+// alignment).
+void geometry(int ncu_slots, int rows_cfg, Args* a) {
   const int64_t per_wg_min = (int64_t)kp::kThreads * kp::kR * 2;
   int64_t rows = (per_wg_min + (int64_t)a->nx * a->nplanes - 1) / ((int64_t)a->nx * a->nplanes);
+  if (rows_cfg > 0) rows = rows_cfg;
   rows = std::max<int64_t>(rows, (a->ny + ncu_slots - 1) / ncu_slots);
   rows = std::max<int64_t>(1, std::min<int64_t>(rows, a->ny));
   if ((a->nx & 1) && (rows & 1) && rows < a->ny) ++rows;
@@ -708,7 +859,7 @@ int prepare(kp_ctx* ctx, Args* a) {
     snprintf(ctx->err, sizeof(ctx->err), "the persistent kernel does not fit on a CU");
     return KP_EHIP;
   }
-  geometry(ctx->ncu * occ, a);
+  geometry(ctx->ncu * occ, ctx->cfg.rows_per_wg, a);
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->part), &ctx->part_bytes,
                  (size_t)kp::kPartBuffers * a->nwg * kp::kKStride * sizeof(double))))
     return rc;
@@ -759,14 +910,14 @@ int launch_init(kp_ctx* ctx, const Args& a, int m_target) {
   return KP_OK;
 }
 
-int fill_info(kp_ctx* ctx, kp_info* info) {
+int fill_info_from(kp_ctx* ctx, const Args& a, kp_info* info) {
   KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   State h;
-  KP_HIP(ctx, hipMemcpy(&h, ctx->st, offsetof(State, sigma), hipMemcpyDeviceToHost));
+  KP_HIP(ctx, hipMemcpy(&h, a.st, offsetof(State, sigma), hipMemcpyDeviceToHost));
   Pub pb;
-  KP_HIP(ctx, hipMemcpy(&pb, ctx->pub, sizeof(Pub), hipMemcpyDeviceToHost));
+  KP_HIP(ctx, hipMemcpy(&pb, a.pub, sizeof(Pub), hipMemcpyDeviceToHost));
   unsigned flags[16] = {0};
-  KP_HIP(ctx, hipMemcpy(flags, ctx->sync, sizeof(flags), hipMemcpyDeviceToHost));
+  KP_HIP(ctx, hipMemcpy(flags, a.sync, sizeof(flags), hipMemcpyDeviceToHost));
   std::memset(info, 0, sizeof(*info));
   info->status = flags[kp::kSyncAbort] ? KP_STATUS_ABORTED : pb.status;
   info->substeps = h.substeps;
@@ -782,6 +933,8 @@ int fill_info(kp_ctx* ctx, kp_info* info) {
   info->t_end = h.t;
   return KP_OK;
 }
+
+int fill_info(kp_ctx* ctx, kp_info* info) { return fill_info_from(ctx, ctx->last, info); }
 
 // ---- batched call: plan, workspace, graph -------------------------------------
 
@@ -1080,7 +1233,16 @@ void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ti
 
 extern "C" {
 
-int kp_version(void) { return 10200; }
+int kp_version(void) { return 10300; }
+
+int kp_runtime_version(int32_t* runtime_host, int32_t* driver_host) {
+  int rv = 0, dv = 0;
+  if (hipRuntimeGetVersion(&rv) != hipSuccess) return KP_EHIP;
+  if (hipDriverGetVersion(&dv) != hipSuccess) return KP_EHIP;
+  if (runtime_host) *runtime_host = rv;
+  if (driver_host) *driver_host = dv;
+  return KP_OK;
+}
 
 const char* kp_strerror(int code) {
   switch (code) {
@@ -1124,8 +1286,8 @@ int kp_destroy(kp_ctx* ctx) {
   if (!ctx) return KP_EINVAL;
   if (ctx->ncu > 0) hipStreamSynchronize(ctx->stream);
   batch_free(ctx->batch);
-  void* bufs[] = {ctx->V,  ctx->u,    ctx->part, ctx->hx, ctx->flags,
-                  ctx->st, ctx->pub, ctx->sync, ctx->ex, ctx->tx, ctx->aux};
+  void* bufs[] = {ctx->V,  ctx->u,    ctx->part, ctx->hx, ctx->flags, ctx->st,
+                  ctx->pub, ctx->sync, ctx->ex, ctx->tx, ctx->aux, ctx->integ};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete ctx;
@@ -1142,6 +1304,7 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_
   if ((rc = launch_init(ctx, a, m0))) return rc;
   if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;
+  ctx->st_last = a.st;
   ctx->have_begin = 0;
   if (info) return fill_info(ctx, info);
   return KP_OK;
@@ -1186,6 +1349,7 @@ int kp_phi_combo_tangent(kp_ctx* ctx, const kp_op* A, const kp_op* dA, const dou
   if ((rc = launch_init(ctx, a, m0))) return rc;
   if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;
+  ctx->st_last = a.st;
   ctx->have_begin = 0;
   if (info) return fill_info(ctx, info);
   return KP_OK;
@@ -1293,16 +1457,222 @@ int kp_phi_combo_backward(kp_ctx* ctx, const kp_op* A, const double* B, int32_t 
   return KP_OK;
 }
 
+// ---- exponential integrators ---------------------------------------------------
+
+namespace {
+
+// Coefficient matrices alpha_{m,i} of Section 4.1 (rows m = 1..M, columns
+// i = 1..P; the first row is zero).
+const double kEpi4[3][2] = {{0.0, 0.0}, {-3.0 / 10.0, 3.0 / 40.0}, {32.0 / 5.0, -11.0 / 10.0}};
+const double kEpi5[4][3] = {{0.0, 0.0, 0.0},
+                            {-4.0 / 5.0, 2.0 / 5.0, -4.0 / 45.0},
+                            {12.0, -9.0 / 2.0, 8.0 / 9.0},
+                            {3.0, 0.0, -1.0 / 3.0}};
+
+struct Integ {
+  kp_ctx* ctx;
+  kp::RhsK rk;
+  kp_rhs rhs;
+  int64_t n;
+  double tol;
+  int m_max;
+  kp_info* info;
+  int worst = KP_STATUS_OK;
+  double *fn, *jd, *B, *y, *z, *fz;
+
+  unsigned grid() const { return (unsigned)((n + 255) / 256); }
+
+  // the Jacobian of f at un (its ADR field is jd, computed with f(un))
+  kp_op jac(const double* un) const {
+    kp_op J{};
+    J.nx = rhs.nx;
+    J.ny = rhs.ny;
+    J.dx = rhs.dx;
+    J.dy = rhs.dy;
+    J.nu = rhs.nu;
+    J.brus_a = 1.0;
+    J.brus_b = 3.0;
+    if (rhs.kind == KP_RHS_ALLEN_CAHN) {
+      J.kind = KP_OP_ALLEN_CAHN;
+      J.field0 = un;
+    } else {
+      J.kind = KP_OP_ADR;
+      J.ax = rhs.ax;
+      J.ay = rhs.ay;
+      J.field0 = jd;
+    }
+    return J;
+  }
+
+  int phi(const kp_op& J, int p, double h) {
+    kp_info r;
+    const int rc = kp_phi_combo(ctx, &J, B, p, n, h, tol, m_max, y, info ? &r : nullptr);
+    if (rc || !info) return rc;
+    worst = std::max(worst, (int)r.status);
+    info->substeps += r.substeps;
+    info->rejected += r.rejected;
+    info->arnoldi_steps += r.arnoldi_steps;
+    info->expm_evals += r.expm_evals;
+    info->n_fallback += r.n_fallback;
+    info->breakdowns += r.breakdowns;
+    info->m_last = r.m_last;
+    info->err_max = std::max(info->err_max, r.err_max);
+    return KP_OK;
+  }
+
+  int launched() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KP_OK : hip_fail(ctx, e, "integrator kernel");
+  }
+
+  // f(u) into f (and the ADR Jacobian field into jd when want_jd)
+  int rhs_at(const double* u, double* f, bool want_jd, double* Bcols) {
+    hipLaunchKernelGGL(kp::k_rhs, dim3(grid()), dim3(256), 0, ctx->stream, rk, u, f,
+                       want_jd ? jd : nullptr, Bcols, (int64_t)n);
+    return launched();
+  }
+
+  int axpy(double* out, const double* a) {
+    hipLaunchKernelGGL(kp::k_axpy, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)),
+                       dim3(256), 0, ctx->stream, out, a, (const double*)y, (int64_t)n);
+    return launched();
+  }
+
+  // one SRERK3 step of size h from u_in to u_out (u_out may equal u_in)
+  int srerk3(const double* u_in, double* u_out, double h) {
+    int rc;
+    if ((rc = rhs_at(u_in, fn, true, B))) return rc;      // B = [0, f_n]
+    const kp_op J = jac(u_in);
+    if ((rc = phi(J, 1, 0.75 * h))) return rc;
+    if ((rc = axpy(z, u_in))) return rc;                  // z = u_n + y
+    if ((rc = rhs_at(z, fz, false, nullptr))) return rc;
+    hipLaunchKernelGGL(kp::k_srerk_cols, dim3(grid()), dim3(256), 0, ctx->stream, rk, u_in,
+                       (const double*)fn, (const double*)z, (const double*)fz,
+                       (32.0 / 9.0) / (h * h), B, (int64_t)n);
+    if ((rc = launched())) return rc;
+    if ((rc = phi(J, 3, h))) return rc;
+    return axpy(u_out, u_in);
+  }
+};
+
+}  // namespace
+
+int kp_integrate(kp_ctx* ctx, const kp_rhs* f, int32_t method, double dt, int32_t nsteps,
+                 int32_t start_substeps, double* u, double tol, int32_t m_max, kp_info* info) {
+  if (!ctx || !f || !u) return KP_EINVAL;
+  if (f->kind != KP_RHS_ALLEN_CAHN && f->kind != KP_RHS_ADR) return KP_EINVAL;
+  if (f->nx < 1 || f->ny < 1 || (int64_t)f->nx * f->ny > ((int64_t)1 << 30)) return KP_EINVAL;
+  const double vals[] = {f->dx, f->dy, f->nu, f->ax, f->ay, f->gamma, dt};
+  for (double v : vals)
+    if (!std::isfinite(v)) return KP_EINVAL;
+  if (!(f->dx > 0.0) || !(f->dy > 0.0) || !(dt > 0.0) || nsteps < 0) return KP_EINVAL;
+  if (method != KP_EPI4 && method != KP_EPI5 && method != KP_SRERK3) return KP_EINVAL;
+  if (method != KP_SRERK3 && start_substeps < 1) return KP_EINVAL;
+  if (m_max < 1 || m_max > KP_MMAX) return KP_EINVAL;
+  if (ctx->cfg.fixed_m == 0 && !(tol > 0.0 && std::isfinite(tol))) return KP_EINVAL;
+  int rc = device_setup(ctx);
+  if (rc) return rc;
+  const int P = method == KP_EPI4 ? 2 : (method == KP_EPI5 ? 3 : 0);
+  const int M = method == KP_EPI4 ? 3 : 4;      // SRERK3 uses p = 3
+  const int64_t n = (int64_t)f->nx * f->ny;
+  // workspace: states u_{n-k} and f(u_{n-k}) (k <= P), B (M + 1 columns),
+  // y, z, f(z), the ADR Jacobian field
+  const size_t need = sizeof(double) * (size_t)n * (2 * (P + 1) + (M + 1) + 4);
+  if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->integ), &ctx->integ_bytes, need))) return rc;
+  double* ws = ctx->integ;
+  double* ru = ws;                                   // ring of states, P + 1 slots
+  double* rf = ru + (size_t)(P + 1) * n;             // ring of f values
+  Integ g;
+  g.ctx = ctx;
+  g.rhs = *f;
+  g.rk.kind = f->kind;
+  g.rk.nx = f->nx;
+  g.rk.ny = f->ny;
+  g.rk.cx = f->nu / (f->dx * f->dx);
+  g.rk.cy = f->nu / (f->dy * f->dy);
+  g.rk.adx = f->ax / (2.0 * f->dx);
+  g.rk.ady = f->ay / (2.0 * f->dy);
+  g.rk.gamma = f->gamma;
+  g.n = n;
+  g.tol = tol;
+  g.m_max = m_max;
+  g.info = info;
+  g.B = rf + (size_t)(P + 1) * n;
+  g.y = g.B + (size_t)(M + 1) * n;
+  g.z = g.y + n;
+  g.fz = g.z + n;
+  g.jd = g.fz + n;
+  g.fn = rf;                                         // SRERK3: f_n in ring slot 0
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (method == KP_SRERK3) {
+    for (int s = 0; s < nsteps; ++s)
+      if ((rc = g.srerk3(u, u, dt))) return rc;
+  } else {
+    // slot (cur - k) mod (P + 1) holds u_{n-k}
+    KP_HIP(ctx, hipMemcpyAsync(ru, u, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    int cur = 0;
+    auto slot_u = [&](int k) { return ru + (size_t)((cur - k + (P + 1)) % (P + 1)) * n; };
+    auto slot_f = [&](int k) { return rf + (size_t)((cur - k + (P + 1)) % (P + 1)) * n; };
+    // the first P states by SRERK3 substeps (the f ring, filled after, is
+    // their scratch meanwhile: g.fn is its slot 0)
+    const int nstart = std::min(P, (int)nsteps);
+    for (int k = 0; k < nstart; ++k) {
+      double* nxt = ru + (size_t)((cur + 1) % (P + 1)) * n;
+      KP_HIP(ctx, hipMemcpyAsync(nxt, slot_u(0), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+      for (int s = 0; s < start_substeps; ++s)
+        if ((rc = g.srerk3(nxt, nxt, dt / start_substeps))) return rc;
+      cur = (cur + 1) % (P + 1);
+    }
+    const double* Ep = method == KP_EPI4 ? &kEpi4[0][0] : &kEpi5[0][0];
+    kp::EpiK q{};
+    q.M = M;
+    q.P = P;
+    for (int m = 0; m < M; ++m) {
+      for (int i = 0; i < P; ++i) q.alpha[m][i] = Ep[m * P + i];
+      q.hinv[m] = 1.0 / std::pow(dt, (double)m);
+    }
+    if (nsteps > nstart) {
+      // f of the states in the ring (and, for the newest, the Jacobian field)
+      for (int k = nstart; k >= 0; --k)
+        if ((rc = g.rhs_at(slot_u(k), slot_f(k), k == 0, nullptr))) return rc;
+    }
+    for (int s = nstart; s < nsteps; ++s) {
+      for (int k = 0; k <= P; ++k) {
+        q.u[k] = slot_u(k);
+        q.f[k] = slot_f(k);
+      }
+      hipLaunchKernelGGL(kp::k_epi_cols, dim3(g.grid()), dim3(256), 0, ctx->stream, g.rk, q,
+                         g.B, (int64_t)n);
+      if ((rc = g.launched())) return rc;
+      if ((rc = g.phi(g.jac(slot_u(0)), M, dt))) return rc;
+      double* nxt = slot_u(P);                       // the oldest state is no longer read
+      if ((rc = g.axpy(nxt, slot_u(0)))) return rc;
+      cur = (cur + 1) % (P + 1);
+      if ((rc = g.rhs_at(slot_u(0), slot_f(0), true, nullptr))) return rc;
+    }
+    KP_HIP(ctx, hipMemcpyAsync(u, slot_u(0), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  }
+  if (info) {
+    KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    info->status = g.worst;
+    info->t_end = dt * nsteps;
+  }
+  return KP_OK;
+}
+
 int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap) {
   if (!ctx || cap < 0 || (cap > 0 && (!tau_host || !m_host))) return KP_EINVAL;
-  if (!ctx->st) return KP_ESTATE;
+  const State* st = ctx->st_last;
+  if (!st) return KP_ESTATE;
   KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   int nlog = 0;
-  KP_HIP(ctx, hipMemcpy(&nlog, &ctx->st->nlog, sizeof(int), hipMemcpyDeviceToHost));
+  KP_HIP(ctx, hipMemcpy(&nlog, &st->nlog, sizeof(int), hipMemcpyDeviceToHost));
   const int n = std::min(std::min(nlog, kp::kLogMax), cap);
   if (n > 0) {
-    KP_HIP(ctx, hipMemcpy(tau_host, ctx->st->log_tau, n * sizeof(double), hipMemcpyDeviceToHost));
-    KP_HIP(ctx, hipMemcpy(m_host, ctx->st->log_m, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    KP_HIP(ctx, hipMemcpy(tau_host, st->log_tau, n * sizeof(double), hipMemcpyDeviceToHost));
+    KP_HIP(ctx, hipMemcpy(m_host, st->log_m, n * sizeof(int32_t), hipMemcpyDeviceToHost));
   }
   return n;
 }

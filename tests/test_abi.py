@@ -32,7 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_constants_match_header():
     text = open(HEADER).read()
     for name in ("KP_OK", "KP_EINVAL", "KP_EUNSUPPORTED", "KP_ORTH_H_GSMGS", "KP_ORTH_H_NCWY",
-                 "KP_OP_BRUSSELATOR", "KP_BASIS_F32", "KP_MMAX", "KP_PMAX",
+                 "KP_ORTH_MGS", "KP_ORTH_IOCGS", "KP_CTRL_PI", "KP_RHS_ADR", "KP_SRERK3",
+                 "KP_EPI5", "KP_OP_BRUSSELATOR", "KP_BASIS_F32", "KP_MMAX", "KP_PMAX",
                  "KP_STATUS_NONFINITE"):
         m = re.search(rf"#define\s+{name}\s+(-?\d+)", text)
         assert m and int(m.group(1)) == getattr(_lib, name), name
@@ -46,7 +47,8 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"kp_op": _lib.KpOp, "kp_config": _lib.KpConfig, "kp_info": _lib.KpInfo}
+    structs = {"kp_op": _lib.KpOp, "kp_config": _lib.KpConfig, "kp_info": _lib.KpInfo,
+               "kp_rhs": _lib.KpRhs}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "krylov_phi.h"',
              "int main(void) {"]
     for cname, cls in structs.items():
@@ -68,14 +70,14 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_version_and_strerror():
     lib = _lib.load()
-    assert lib.kp_version() == 10200
+    assert lib.kp_version() == 10300
     assert lib.kp_strerror(-1) == b"invalid argument"
     assert lib.kp_strerror(12345) == b"unknown error"
 
 
 def _ctx(**kw):
     lib = _lib.load()
-    cfg = _lib.KpConfig(None, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0)
+    cfg = _lib.KpConfig(None, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0, 0)
     for k, v in kw.items():
         setattr(cfg, k, v)
     h = ctypes.c_void_p()
@@ -83,7 +85,7 @@ def _ctx(**kw):
     return lib, h, rc
 
 
-@pytest.mark.parametrize("field,val", [("orth", 7), ("basis_dtype", 3), ("m_init", 65),
+@pytest.mark.parametrize("field,val", [("orth", 7), ("orth", 5), ("basis_dtype", 3), ("m_init", 65), ("controller", 2), ("rows_per_wg", -1),
                                        ("m_init", -1), ("tau_init", -1.0),
                                        ("tau_init", float("inf")), ("fixed_m", 65),
                                        ("max_substeps", -2)])
@@ -184,3 +186,27 @@ def test_batched_rejects_empty_and_missing_arrays():
                                         None) == _lib.KP_EINVAL
     finally:
         lib.kp_destroy(h)
+
+
+def test_integrate_rejects_bad_arguments():
+    lib, h, rc = _ctx()
+    assert rc == 0
+    try:
+        def rhs(**kw):
+            base = dict(kind=0, nx=8, ny=8, reserved=0, dx=0.125, dy=0.125, nu=0.1, ax=0.0,
+                        ay=0.0, gamma=0.0)
+            base.update(kw)
+            return _lib.KpRhs(**base)
+        good = dict(method=0, dt=0.01, nsteps=2, start=4, u=FAKE, tol=1e-8, m_max=16)
+        for r, kw in [(rhs(kind=2), {}), (rhs(nx=0), {}), (rhs(dx=0.0), {}),
+                      (rhs(nu=float("nan")), {}), (rhs(), dict(method=3)),
+                      (rhs(), dict(dt=0.0)), (rhs(), dict(nsteps=-1)), (rhs(), dict(start=0)),
+                      (rhs(), dict(u=None)), (rhs(), dict(tol=0.0)), (rhs(), dict(m_max=65))]:
+            a = dict(good)
+            a.update(kw)
+            assert lib.kp_integrate(h, ctypes.byref(r), a["method"], a["dt"], a["nsteps"],
+                                    a["start"], a["u"], a["tol"], a["m_max"], None) \
+                == _lib.KP_EINVAL, kw
+    finally:
+        lib.kp_destroy(h)
+

@@ -33,9 +33,19 @@ def test_measured_traffic_only_for_matching_sources(tmp_path):
     assert bench.measured_traffic(str(tmp_path / "missing.txt")) is None
 
 
-def test_committed_summaries_match_the_current_sources():
-    assert bench.measured_traffic() is not None
-    assert bench.measured_traffic(bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call") is not None
+def test_committed_summaries_parse():
+    """The committed counter summaries carry the source hash they were taken
+    on and the byte counts bench.py reads (reported only while the hash
+    matches the current sources)."""
+    for path, key in ((bench.TRAFFIC_FILE, "hbm_bytes_per_launch"),
+                      (bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call")):
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        assert len(kv["source_sha256"]) == 64
+        assert float(kv[key]) > 0.0
 
 
 def test_basis_bytes_of_a_small_schedule_by_hand():
@@ -54,3 +64,26 @@ def test_basis_bytes_with_float64_basis_match_the_vector_passes():
         n = 1000
         assert bench.basis_bytes_per_call(sched, p, c, n, 8) == \
             bench.vectors_per_call(sched, p, c) * 8 * n
+
+
+def test_vector_passes_of_mgs_and_iocgs_by_hand():
+    # p = 2, c = 1, one substep of m = 2.  Stage 4, combine 3, out 1 (as above).
+    # MGS step 0: matvec reads x_0 (from u), B (2), u (1), writes w and column
+    # 0 (2): 6; the norm pass reads w and x_0, writes w: 3 -> 9.  Step 1:
+    # matvec reads x_1, B, u, writes w, reads x_0: 6; the second inner product
+    # reads w, x_0, x_1 and writes w: 4; the norm pass: 3 -> 13.
+    assert bench.vectors_per_call([(0.1, 2)], 2, 1, "mgs") == 4 + (9 + 13) + 3 + 1
+    # ioCGS step 0 as MGS (9); step 1: matvec with x_0 . w (6), one pass reads
+    # w, x_0, x_1 and writes w (4) -> 10.
+    assert bench.vectors_per_call([(0.1, 2)], 2, 1, "iocgs") == 4 + (9 + 10) + 3 + 1
+    # the reductions of a step: j + 1 for MGS (Algorithm 1), two for ioCGS
+    assert [bench.syncs_per_step(jj, "mgs") for jj in range(3)] == [2, 3, 4]
+    assert [bench.syncs_per_step(jj, "iocgs") for jj in range(3)] == [2, 2, 2]
+    assert [bench.syncs_per_step(jj, "h-cwy") for jj in range(3)] == [1, 1, 1]
+
+
+def test_error_metrics():
+    import numpy as np
+    ref = np.array([1.0, -2.0, 2.0])
+    e = bench.errors(ref + np.array([0.0, 0.03, 0.0]), ref)
+    assert abs(e["rel_l2"] - 0.01) < 1e-15 and abs(e["max_abs_rel"] - 0.015) < 1e-15
