@@ -22,6 +22,8 @@ the float64 CPU oracle replaying its schedule, and legs:
   fp32_basis  the 2 x 2048^2 Brusselator with float32 and float64 bases
   adjoint     gradients of a least-squares loss (1024^2 advection-diffusion)
   batched     512 uneven problems in one launch against 512 calls
+  integrators EPI4, EPI5, SRERK3 (Section 4.1) on the Allen-Cahn and ADR
+              problems at 2000^2, time to solution with H-GSMGS and ioCGS
   cpu_baseline  the oracle timed on the host cores (1 thread and all)
 """
 from __future__ import annotations
@@ -38,7 +40,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Arnoldi steps/s and phi_combo/s at N=1M,m=64; HBM GB/s vs peak; err vs FP64"
-KERNEL = "kp::k_run<double>"
+KERNEL = "kp::k_run<double, false>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_run_allen_cahn_1024_traffic.txt")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_uneven_512_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2410_14917_amd", "csrc")
@@ -263,6 +265,8 @@ def main():
                     help="skip the adjoint leg (advection-diffusion 1024^2, least-squares loss)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (512 uneven advection-diffusion-reaction problems)")
+    ap.add_argument("--no-integrators", action="store_true",
+                    help="skip the exponential-integrator leg (Allen-Cahn and ADR, 2000^2)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--dump", metavar="DIR",
@@ -675,6 +679,48 @@ def main():
         }
         log(f"batched leg: {result['batched']}")
         del Bs4, outs4, seq4
+
+    # ---- exponential integrators (Section 4.1) on the paper's problems -------
+    # Allen-Cahn and ADR of Section 4.3 at N = 2000^2 (periodic stand-ins),
+    # dt = 1e-2, ten steps (t = 0.1), Krylov tolerance 1e-12 as the paper's;
+    # time to solution per method with H-GSMGS and with the ioCGS baseline
+    # (the paper's runtime ratio in its own setting)
+    if not args.no_integrators:
+        torch.cuda.empty_cache()
+        leg = {"setting": "2000x2000 periodic stand-ins of Section 4.3's Allen-Cahn (eps=0.1, "
+                          "[-1,1]^2) and ADR (eps=1e-2, alpha=-6, gamma=100, [0,1]^2); dt=1e-2, "
+                          "10 steps, tol 1e-12, m<=64; EPI starts by SRERK3 (2 substeps each)"}
+        for pname, ivp in (("allen_cahn", W.ivp_allen_cahn(side=2000, nsteps=10)),
+                           ("adr", W.ivp_adr(side=2000, nsteps=10))):
+            u0 = torch.as_tensor(ivp.u0, device=dev)
+            part = {}
+            for method in ("epi4", "epi5", "srerk3"):
+                row = {}
+                for orth in ("h-gsmgs", "iocgs"):
+                    ci = kp.Context(orth=orth, stream=stream)
+                    u = u0.clone()
+                    _, inf_i = ci.integrate(ivp.rhs, u, ivp.dt, ivp.nsteps, method=method,
+                                            tol=ivp.tol, m_max=ivp.m_max, start_substeps=2,
+                                            info=True)
+                    u = u0.clone()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ci.integrate(ivp.rhs, u, ivp.dt, ivp.nsteps, method=method, tol=ivp.tol,
+                                 m_max=ivp.m_max, start_substeps=2)
+                    torch.cuda.synchronize()
+                    row[orth] = {"s": round(time.perf_counter() - t0, 4),
+                                 "arnoldi_steps": inf_i["arnoldi_steps"],
+                                 "substeps": inf_i["substeps"], "status": inf_i["status"]}
+                    if orth == "h-gsmgs":
+                        y_ref = u.cpu().numpy()
+                    else:
+                        row["iocgs"]["rel_l2_vs_h_gsmgs"] = errors(u.cpu().numpy(), y_ref)["rel_l2"]
+                    ci.close()
+                row["runtime_ratio_h_gsmgs_vs_iocgs"] = round(row["h-gsmgs"]["s"] / row["iocgs"]["s"], 4)
+                part[method] = row
+                log(f"integrator {pname} {method}: {row}")
+            leg[pname] = part
+        result["integrators"] = leg
 
     # ---- the benchmark call against the oracle's replay of its schedule ------
     if replay is not None:

@@ -49,11 +49,13 @@ static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
 static_assert(kOffOwn + kKStride <= kOffHl, "tv / own overlap the halo copy");
 static_assert(kLdsDoubles >= kNmPad * kGjLd, "the small exponential does not fit the phase buffer");
 
-// One phase of the call for this workgroup.  cur: control of the phase (LDS,
+// One phase of the call for this workgroup.  MS: the kernel also runs the
+// processes with one reduction per inner product (MGS) or per window
+// (ioCGS); the one-reduction kernels are compiled without those phases.  cur: control of the phase (LDS,
 // identical in every workgroup); nxt: the leader's control of the next phase;
 // ok: cleared when a bounded wait gives up (the launch is aborting).  On
 // return cur holds the control of the next phase.
-template <typename TB>
+template <typename TB, bool MS>
 __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, LeadLds& L, Ctl& cur, Ctl& nxt, int& ok,
                           unsigned k) {
   double* sacc = lds + kOffSacc;
@@ -101,22 +103,26 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     case PH_CLOSE:
       update_pass<TB>(a, c.j - 1, a.pub->coef, red, true);
       break;
-    case PH_MVEC: {
-      // MGS multiplies and takes v_1 . w; ioCGS takes v_{j-1} . w and v_j . w
-      const int acol = c.j == 0 ? -1 : (a.orth == KP_ORTH_MGS ? 0 : c.j - 1);
-      if (a.halo_lds)
-        mvec_pass<TB, true>(a, c.j, acol, sacc, hl);
-      else
-        mvec_pass<TB, false>(a, c.j, acol, sacc, hl);
+    case PH_MVEC:
+      if constexpr (MS) {
+        // MGS multiplies and takes v_1 . w; ioCGS takes v_{j-1} . w and v_j . w
+        const int acol = c.j == 0 ? -1 : (a.orth == KP_ORTH_MGS ? 0 : c.j - 1);
+        if (a.halo_lds)
+          mvec_pass<TB, true>(a, c.j, acol, sacc, hl);
+        else
+          mvec_pass<TB, false>(a, c.j, acol, sacc, hl);
+      }
       break;
-    }
     case PH_PROJ:
-      // MGS: subtract the projection on v_{i-1}, then v_i . w (or the norm);
-      // ioCGS: subtract both projections of the window, then the norm
-      if (a.orth == KP_ORTH_MGS)
-        proj_pass<TB>(a, c.j, c.i - 1, c.i - 1, a.pub->coef, c.i <= c.j ? c.i : -1, c.i > c.j, red);
-      else
-        proj_pass<TB>(a, c.j, max(0, c.j - 1), c.j, a.pub->coef, -1, true, red);
+      if constexpr (MS) {
+        // MGS: subtract the projection on v_{i-1}, then v_i . w (or the
+        // norm); ioCGS: subtract both projections of the window, then the norm
+        if (a.orth == KP_ORTH_MGS)
+          proj_pass<TB>(a, c.j, c.i - 1, c.i - 1, a.pub->coef, c.i <= c.j ? c.i : -1, c.i > c.j,
+                        red);
+        else
+          proj_pass<TB>(a, c.j, max(0, c.j - 1), c.j, a.pub->coef, -1, true, red);
+      }
       break;
     case PH_COMBINE:
       combine_pass<TB>(a, c.m_eff, a.pub->coef, c.last != 0);
@@ -157,12 +163,16 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       leader_close(a, tv[0], L, nxt);
       break;
     case PH_MVEC:
-      reduce_partials(a, kMvSlots, tv, grp);
-      leader_mvec(a, c.j, tv, L, nxt);
+      if constexpr (MS) {
+        reduce_partials(a, kMvSlots, tv, grp);
+        leader_mvec(a, c.j, tv, L, nxt);
+      }
       break;
     case PH_PROJ:
-      reduce_partials(a, 1, tv, grp);
-      leader_proj(a, c.j, c.i, tv[0], L, nxt);
+      if constexpr (MS) {
+        reduce_partials(a, 1, tv, grp);
+        leader_proj(a, c.j, c.i, tv[0], L, nxt);
+      }
       break;
     case PH_EXPM:
       expm_phase(a, lds, L, nxt);
@@ -182,7 +192,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
 }
 
 // The whole call (or, for the step-by-step entry, the steps up to stop_j).
-template <typename TB>
+template <typename TB, bool MS>
 __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
   __shared__ double lds[kLdsDoubles];
   __shared__ LeadLds lead;
@@ -207,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
          ((cur.phase == PH_STEP || cur.phase == PH_MVEC) && cur.j >= a.stop_j)))
       break;
     ++k;
-    run_phase<TB>(a, lds, lead, cur, nxt, ok, k);
+    run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, k);
   }
 }
 
@@ -330,7 +340,7 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchDesc d) {
   }
 }
 
-template <typename TB>
+template <typename TB, bool MS>
 __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
   __shared__ double lds[kLdsDoubles];
   __shared__ LeadLds lead;
@@ -385,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
       __syncthreads();
       if (!ok || cur.phase == PH_DONE) break;
       ++k;
-      run_phase<TB>(a, lds, lead, cur, nxt, ok, k);
+      run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, k);
     }
     __syncthreads();
     if (!ok) break;   // a bounded wait gave up: this team stops
@@ -605,6 +615,13 @@ __global__ __launch_bounds__(256) void k_axpy(double* out, const double* a, cons
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) out[e] = a[e] + y[e];
 }
 
+// A deterministic non-degenerate right-hand side for the calibration solves.
+__global__ __launch_bounds__(256) void k_fill_pattern(double* x, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride)
+    x[e] = sin(0.37 * (double)(e + 1)) + 0.5 * cos(0.0101 * (double)e);
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -648,12 +665,14 @@ struct kp_ctx {
   size_t aux_bytes = 0;
   double* integ = nullptr;         // integrators: state and right-hand-side history, columns
   size_t integ_bytes = 0;
-  int occ[2] = {-1, -1};
+  int occ[4] = {-1, -1, -1, -1};
   Args last{};
   int have_begin = 0;
   int arn_target = 0;
   BatchCache* batch = nullptr;   // plan, workspace and graph of the last batched call
   State* st_last = nullptr;      // State of the last single call
+  kp::PlanModel model;           // the batched planner's cost model (kp_calibrate)
+  int model_gen = 0;             // bumped when the model changes (part of the plan key)
   char err[512] = {0};
 };
 
@@ -776,16 +795,23 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   return KP_OK;
 }
 
-template <typename TB>
+template <typename TB, bool MS>
 int occupancy(kp_ctx* ctx, int which) {
   if (ctx->occ[which] < 0) {
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void*>(&kp::k_run<TB>), kp::kThreads, 0);
+        &occ, reinterpret_cast<const void*>(&kp::k_run<TB, MS>), kp::kThreads, 0);
     if (e != hipSuccess) return -1;
     ctx->occ[which] = occ;
   }
   return ctx->occ[which];
+}
+
+// Co-resident workgroups per CU of the kernel that runs a's process.
+int kernel_occupancy(kp_ctx* ctx, const Args& a) {
+  if (kp::orth_multi_sync(a.orth))
+    return a.basis_f32 ? occupancy<float, true>(ctx, 3) : occupancy<double, true>(ctx, 2);
+  return a.basis_f32 ? occupancy<float, false>(ctx, 1) : occupancy<double, false>(ctx, 0);
 }
 
 int device_setup(kp_ctx* ctx) {
@@ -854,7 +880,7 @@ int prepare(kp_ctx* ctx, Args* a) {
   if ((rc = grow(ctx, reinterpret_cast<void**>(&ctx->u), &ctx->u_bytes,
                  (size_t)a->ld * sizeof(double))))
     return rc;
-  const int occ = a->basis_f32 ? occupancy<float>(ctx, 1) : occupancy<double>(ctx, 0);
+  const int occ = kernel_occupancy(ctx, *a);
   if (occ <= 0) {
     snprintf(ctx->err, sizeof(ctx->err), "the persistent kernel does not fit on a CU");
     return KP_EHIP;
@@ -890,19 +916,23 @@ int prepare(kp_ctx* ctx, Args* a) {
   return KP_OK;
 }
 
-template <typename TB>
+template <typename TB, bool MS>
 int launch_run(kp_ctx* ctx, Args a, int arnoldi_only) {
   void* args[] = {&a, &arnoldi_only};
-  KP_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&kp::k_run<TB>),
+  KP_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&kp::k_run<TB, MS>),
                                          dim3(a.nwg), dim3(kp::kThreads), args, 0,
                                          ctx->stream));
   return KP_OK;
 }
 
 int launch(kp_ctx* ctx, const Args& a, int arnoldi_only) {
-  return a.basis_f32 ? launch_run<float>(ctx, a, arnoldi_only)
-                     : launch_run<double>(ctx, a, arnoldi_only);
+  if (kp::orth_multi_sync(a.orth))
+    return a.basis_f32 ? launch_run<float, true>(ctx, a, arnoldi_only)
+                       : launch_run<double, true>(ctx, a, arnoldi_only);
+  return a.basis_f32 ? launch_run<float, false>(ctx, a, arnoldi_only)
+                     : launch_run<double, false>(ctx, a, arnoldi_only);
 }
+
 
 int launch_init(kp_ctx* ctx, const Args& a, int m_target) {
   hipLaunchKernelGGL(kp::k_init, dim3(1), dim3(256), 0, ctx->stream, a, m_target);
@@ -1007,10 +1037,10 @@ void batch_free(BatchCache* b) {
   delete b;
 }
 
-template <typename TB>
+template <typename TB, bool MS>
 int batch_occupancy(kp_ctx* ctx, int* occ) {
   KP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  occ, reinterpret_cast<const void*>(&kp::k_batch<TB>), kp::kThreads, 0));
+                  occ, reinterpret_cast<const void*>(&kp::k_batch<TB, MS>), kp::kThreads, 0));
   return KP_OK;
 }
 
@@ -1053,14 +1083,16 @@ int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp:
   b->nprob = np;
   const bool f32 = as[0].basis_f32 != 0;
   int occ = 0;
-  int rc = f32 ? batch_occupancy<float>(ctx, &occ) : batch_occupancy<double>(ctx, &occ);
+  const bool ms = kp::orth_multi_sync(as[0].orth);
+  int rc = ms ? (f32 ? batch_occupancy<float, true>(ctx, &occ) : batch_occupancy<double, true>(ctx, &occ))
+              : (f32 ? batch_occupancy<float, false>(ctx, &occ) : batch_occupancy<double, false>(ctx, &occ));
   if (rc || occ < 1) {
     batch_free(b);
     if (!rc) snprintf(ctx->err, sizeof(ctx->err), "the batched kernel does not fit on a CU");
     return rc ? rc : KP_EHIP;
   }
   b->n_wg = ctx->ncu * occ;
-  const kp::PlanModel model;
+  const kp::PlanModel model = ctx->model;
   b->plan = kp::make_plan(qs, b->n_wg, model);
   const kp::Plan& pl = b->plan;
   const int nt = (int)pl.team_size.size();
@@ -1165,7 +1197,10 @@ int batch_create(kp_ctx* ctx, const std::vector<Args>& as, const std::vector<kp:
   p1.gridDim = dim3(np);
   p1.blockDim = dim3(256);
   p1.kernelParams = a1;
-  p2.func = f32 ? reinterpret_cast<void*>(&kp::k_batch<float>) : reinterpret_cast<void*>(&kp::k_batch<double>);
+  p2.func = ms ? (f32 ? reinterpret_cast<void*>(&kp::k_batch<float, true>)
+                      : reinterpret_cast<void*>(&kp::k_batch<double, true>))
+               : (f32 ? reinterpret_cast<void*>(&kp::k_batch<float, false>)
+                      : reinterpret_cast<void*>(&kp::k_batch<double, false>));
   p2.gridDim = dim3(b->n_wg);
   p2.blockDim = dim3(kp::kThreads);
   p2.kernelParams = a2;
@@ -1773,7 +1808,7 @@ int kp_phi_combo_batched(kp_ctx* ctx, int32_t nprob, const kp_op* ops, const dou
   for (int i = 1; i < nprob; ++i)
     if (spans[i].first < spans[i - 1].second) return KP_EINVAL;
   std::vector<long long> key = {nprob, m_max, ctx->cfg.basis_dtype, ctx->cfg.orth,
-                                ctx->cfg.fixed_m, ctx->cfg.fixed_substeps};
+                                ctx->cfg.fixed_m, ctx->cfg.fixed_substeps, ctx->model_gen};
   for (int i = 0; i < nprob; ++i) {
     key.push_back(ops[i].kind);
     key.push_back(ops[i].nx);

@@ -80,8 +80,10 @@ def test_linear_problem_against_closed_form(method, om):
 
 
 def test_scalar_allen_cahn_closed_form():
-    """A spatially constant state follows u' = u - u^3 exactly; EPI5 with its
-    SRERK3 start meets the closed form to its order's accuracy."""
+    """A spatially constant state follows u' = u - u^3 exactly.  EPI5 with its
+    SRERK3 start (8 substeps) at h = 1/40: the oracle's scalar integration
+    (pinned to converge at fifth order) is 2.4e-9 from the closed form; the
+    GPU state equals it to rounding, uniform in space."""
     import math
     side, u0v, T, nsteps = 32, 0.3, 1.0, 40
     rhs = W.Rhs(W.RHS_ALLEN_CAHN, side, side, 1 / side, 1 / side, nu=0.1)
@@ -91,7 +93,11 @@ def test_scalar_allen_cahn_closed_form():
         ctx.integrate(rhs, u, T / nsteps, nsteps, method="epi5", tol=1e-13, m_max=16,
                       start_substeps=8)
     y = u.cpu().numpy()
-    assert np.ptp(y) <= 1e-14 and abs(y[0] - exact) <= 1e-9
+    small = W.Rhs(W.RHS_ALLEN_CAHN, 4, 4, 1 / 4, 1 / 4, nu=0.1)
+    ref = I.integrate(small, np.full(16, u0v), T / nsteps, nsteps, I.EPI5, I.dense_solver,
+                      start_substeps=8)[0]
+    say(f"  gpu - oracle {y[0] - ref:.2e}, oracle - exact {ref - exact:.2e}")
+    assert np.ptp(y) <= 1e-14 and abs(y[0] - ref) <= 1e-13 and abs(y[0] - exact) <= 5e-9
 
 
 def test_mgs_and_iocgs_inside_the_integrator():
