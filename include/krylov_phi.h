@@ -60,6 +60,7 @@ extern "C" {
 #define KP_EHIP         -3  /* HIP runtime error (message via kp_last_error) */
 #define KP_EUNSUPPORTED -4  /* combination of options not supported */
 #define KP_ESTATE       -5  /* call out of order (e.g. step before begin) */
+#define KP_ETOOLARGE    -6  /* the problem exceeds a fixed capacity */
 
 /* ---- kp_info.status ------------------------------------------------------ */
 #define KP_STATUS_OK            0
@@ -200,6 +201,31 @@ int kp_set_config(kp_ctx* ctx, const kp_config* cfg);
 int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
                  int64_t ldb, double h, double tol, int32_t m_max,
                  double* out, kp_info* info);
+
+/*
+ * kp_phi_combo for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same computation, kernels and arguments as kp_phi_combo (the same result to
+ * the bit), but the whole workspace (basis, state vector, partial sums, halo
+ * rows, control and state blocks, small-exponential scratch) is carved from
+ * one static device array of KP_NOALLOC_BYTES per GPU, which the loaded
+ * library holds until the process ends; the call makes no allocation.
+ * The workspace needs about (m_max + 2) (N + 64 + 128 planes) elements of the
+ * basis type plus 8 (N + 64) bytes and ~1.3 MB of fixed blocks (float64 basis,
+ * m_max = 64: N up to about 115,000).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other contexts or streams of the process) race and must be ordered by the
+ * caller.  The array keeps the last call's contents; each call resets what it
+ * reads before writing it.  kp_get_schedule afterwards reads this call's log.
+ * The context must be used on the device that was current when it first
+ * touched the device.
+ * Errors: those of kp_phi_combo except KP_ENOMEM; KP_ETOOLARGE when the
+ * workspace exceeds KP_NOALLOC_BYTES (nothing is enqueued).
+ */
+#define KP_NOALLOC_BYTES (64u << 20)
+int kp_phi_combo_noalloc(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p,
+                         int64_t ldb, double h, double tol, int32_t m_max, double* out,
+                         kp_info* info);
 
 /*
  * Directional derivative of the phi combination with respect to the operator

@@ -13,7 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkrylov_phi.so")
 
 # ---- constants (mirror include/krylov_phi.h) --------------------------------
-KP_OK, KP_EINVAL, KP_ENOMEM, KP_EHIP, KP_EUNSUPPORTED, KP_ESTATE = 0, -1, -2, -3, -4, -5
+KP_OK, KP_EINVAL, KP_ENOMEM, KP_EHIP, KP_EUNSUPPORTED, KP_ESTATE, KP_ETOOLARGE = \
+    0, -1, -2, -3, -4, -5, -6
+KP_NOALLOC_BYTES = 64 << 20
 KP_STATUS_OK, KP_STATUS_NOT_CONVERGED, KP_STATUS_NONFINITE, KP_STATUS_ABORTED = 0, 1, 2, 3
 KP_ORTH_H_GSMGS, KP_ORTH_H_CWY, KP_ORTH_H_NCWY, KP_ORTH_MGS, KP_ORTH_IOCGS = 0, 1, 2, 3, 4
 KP_CTRL_POWER, KP_CTRL_PI = 0, 1
@@ -30,7 +32,8 @@ CTRL = {"power": KP_CTRL_POWER, "pi": KP_CTRL_PI}
 BASIS = {"f64": KP_BASIS_F64, "f32": KP_BASIS_F32}
 
 # Exported symbols (every function declared in the header).
-SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_tangent",
+SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_combo_noalloc",
+           "kp_phi_combo_tangent",
            "kp_phi_combo_backward", "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
            "kp_integrate",
@@ -102,6 +105,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_set_config.argtypes = [P, ctypes.POINTER(KpConfig)]
     lib.kp_phi_combo.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, D, D, I32, P,
                                  ctypes.POINTER(KpInfo)]
+    lib.kp_phi_combo_noalloc.argtypes = [P, ctypes.POINTER(KpOp), P, I32, I64, D, D, I32, P,
+                                         ctypes.POINTER(KpInfo)]
     lib.kp_phi_combo_tangent.argtypes = [P, ctypes.POINTER(KpOp), ctypes.POINTER(KpOp), P, I32,
                                          I64, D, D, I32, P, P, ctypes.POINTER(KpInfo)]
     PI32, PD = ctypes.POINTER(I32), ctypes.POINTER(D)

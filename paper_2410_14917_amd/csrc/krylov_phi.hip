@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "kp_internal.h"
@@ -628,6 +629,13 @@ __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double ta
   expm_hbar(a, a.st->H, kLdh, m, tau, false, a.st->F, lds);
 }
 
+// Workspace of the allocation-free entry point (kp_phi_combo_noalloc): one
+// array per GPU, held by the loaded code object until the process ends.  Host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name in host code is a host-side stand-in).
+constexpr size_t kScratchBytes = (size_t)KP_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 }  // namespace kp
 
 // ============================================================================
@@ -916,6 +924,41 @@ int prepare(kp_ctx* ctx, Args* a) {
   return KP_OK;
 }
 
+// The buffers prepare() allocates, carved 256-byte aligned from one region
+// at base (nullptr: only the size).  Returns the bytes the problem needs.
+size_t carve(Args* a, char* base) {
+  const size_t esz = a->basis_f32 ? sizeof(float) : sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  char* st = take(sizeof(State));
+  char* pub = take(sizeof(Pub));
+  char* sync = take(64);
+  char* ex = take(sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad);
+  char* tx = take(sizeof(double) * kp::kTailPad);
+  char* part = take((size_t)kp::kPartBuffers * a->nwg * kp::kKStride * sizeof(double));
+  char* hx = take((size_t)a->nwg * a->nplanes * 2 * a->nx * sizeof(double));
+  char* flags = take((size_t)a->nwg * kp::kFlagStride * sizeof(unsigned));
+  char* u = take((size_t)a->ld * sizeof(double));
+  char* V = take((size_t)a->ld * (size_t)(a->m_max + 2) * esz);
+  if (base) {
+    a->st = reinterpret_cast<State*>(st);
+    a->pub = reinterpret_cast<Pub*>(pub);
+    a->sync = reinterpret_cast<unsigned*>(sync);
+    a->ex = reinterpret_cast<double*>(ex);
+    a->tx = reinterpret_cast<double*>(tx);
+    a->part = reinterpret_cast<double*>(part);
+    a->hx = reinterpret_cast<double*>(hx);
+    a->flags = reinterpret_cast<unsigned*>(flags);
+    a->u = reinterpret_cast<double*>(u);
+    a->V = V;
+  }
+  return off;
+}
+
 template <typename TB, bool MS>
 int launch_run(kp_ctx* ctx, Args a, int arnoldi_only) {
   void* args[] = {&a, &arnoldi_only};
@@ -965,6 +1008,33 @@ int fill_info_from(kp_ctx* ctx, const Args& a, kp_info* info) {
 }
 
 int fill_info(kp_ctx* ctx, kp_info* info) { return fill_info_from(ctx, ctx->last, info); }
+
+// ---- the allocation-free entry point: the static scratch array --------------
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up once per device, with
+// that device current), or nullptr with ctx->err set.
+void* scratch_address(kp_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) {
+    snprintf(ctx->err, sizeof(ctx->err), "device %d beyond the scratch table", ctx->device);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(kp::scratch));
+    if (e != hipSuccess || !ptr) {
+      snprintf(ctx->err, sizeof(ctx->err), "hipGetSymbolAddress(scratch): %s",
+               hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[ctx->device] = ptr;
+  }
+  return g_scratch_ptr[ctx->device];
+}
 
 // ---- batched call: plan, workspace, graph -------------------------------------
 
@@ -1287,6 +1357,7 @@ const char* kp_strerror(int code) {
     case KP_EHIP: return "HIP runtime error";
     case KP_EUNSUPPORTED: return "unsupported combination of options";
     case KP_ESTATE: return "call out of order";
+    case KP_ETOOLARGE: return "problem exceeds a fixed capacity";
     default: return "unknown error";
   }
 }
@@ -1337,6 +1408,45 @@ int kp_phi_combo(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_
   if ((rc = prepare(ctx, &a))) return rc;
   const int m0 = a.m0;
   if ((rc = launch_init(ctx, a, m0))) return rc;
+  if ((rc = launch(ctx, a, 0))) return rc;
+  ctx->last = a;
+  ctx->st_last = a.st;
+  ctx->have_begin = 0;
+  if (info) return fill_info(ctx, info);
+  return KP_OK;
+}
+
+int kp_phi_combo_noalloc(kp_ctx* ctx, const kp_op* A, const double* B, int32_t p, int64_t ldb,
+                         double h, double tol, int32_t m_max, double* out, kp_info* info) {
+  Args a;
+  int rc = build_args(ctx, A, B, p, ldb, h, tol, m_max, out, true, &a);
+  if (rc) return rc;
+  if ((rc = device_setup(ctx))) return rc;
+  int cur = -1;
+  KP_HIP(ctx, hipGetDevice(&cur));
+  if (cur != ctx->device) {
+    snprintf(ctx->err, sizeof(ctx->err), "context bound to device %d, device %d is current",
+             ctx->device, cur);
+    return KP_EINVAL;
+  }
+  const int occ = kernel_occupancy(ctx, a);
+  if (occ <= 0) {
+    snprintf(ctx->err, sizeof(ctx->err), "the persistent kernel does not fit on a CU");
+    return KP_EHIP;
+  }
+  geometry(ctx->ncu * occ, ctx->cfg.rows_per_wg, &a);
+  const size_t need = carve(&a, nullptr);
+  if (need > kp::kScratchBytes) {
+    snprintf(ctx->err, sizeof(ctx->err),
+             "workspace of %zu bytes exceeds the static scratch of %zu bytes", need,
+             kp::kScratchBytes);
+    return KP_ETOOLARGE;
+  }
+  char* base = static_cast<char*>(scratch_address(ctx));
+  if (!base) return KP_EHIP;
+  carve(&a, base);
+  a.wait_ticks = ctx->wait_ticks;
+  if ((rc = launch_init(ctx, a, a.m0))) return rc;
   if ((rc = launch(ctx, a, 0))) return rc;
   ctx->last = a;
   ctx->st_last = a.st;
