@@ -656,6 +656,14 @@ def main():
         c4.close()
         diff = max(float(torch.linalg.vector_norm(a - b)) / float(torch.linalg.vector_norm(b))
                    for a, b in zip(outs4, seq4))
+        # the same batch planned with the cost model calibrated on this device
+        c4c = kp.Context(orth=args.orth, stream=stream)
+        cal_src, cal_model = c4c.calibrate()
+        c4c.phi_combo_batched(ops4, Bs4, hs4, tol=tol4, m_max=mm4, outs=seq4)
+        cal_ms = float(np.median(time_launches(
+            torch, stream, lambda: c4c.phi_combo_batched(ops4, Bs4, hs4, tol=tol4, m_max=mm4,
+                                                         outs=seq4), 3)))
+        c4c.close()
         traffic4 = measured_traffic(BATCH_TRAFFIC_FILE, "hbm_bytes_per_call")
         result["batched"] = {
             "workload": f"{len(probs4)} advection-diffusion-reaction problems, sides U{{32..512}}, "
@@ -675,6 +683,8 @@ def main():
                               if traffic4 else None),
             "plan_makespan_ms": round(1e3 * plan_s, 1),
             "plan_balanced_ms": round(1e3 * work_s / 256, 1),
+            "calibrated_plan": {"source": cal_src, "model": cal_model,
+                                "batched_ms": round(cal_ms, 2)},
             "status_ok": all(r["status"] == 0 for r in inf4),
         }
         log(f"batched leg: {result['batched']}")

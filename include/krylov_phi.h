@@ -388,6 +388,26 @@ int kp_batch_plan(int32_t nprob, const kp_op* ops, const int32_t* p, const doubl
                   int32_t m_max, int32_t n_wg, int32_t* team_of_problem, int32_t* team_wg0,
                   int32_t* team_size, int32_t* nteams, double* makespan, double* work);
 
+/*
+ * Calibration of kp_batch_plan's cost model on this device (the batched
+ * call's autotuner): the small exponential's time at m = 64 is measured
+ * directly, and the streaming rate of one workgroup with the whole grid
+ * streaming, the serial time per Arnoldi step, per step of a multi-workgroup
+ * team and per doubling of a team come from a least-squares fit of the model
+ * to seven fixed-schedule advection-diffusion solves (one substep, m = 8..24,
+ * 64 x 64 to 2048 x 1024 grids, one to 256 workgroups).  The context's later
+ * batched calls plan with the result.  With the environment variable
+ * KP_AUTOTUNE_CACHE naming a file, a cached result for this device (GPU
+ * architecture, CU count, library version) is read instead of measuring
+ * unless force != 0, and a measured one is stored there.
+ *   model_host: optional, 5 doubles: bytes/s per workgroup, serial seconds
+ *               per step, per team step, per team doubling, and seconds per
+ *               small exponential at m = 64.
+ * Returns 0 (measured) or 1 (read from the cache), or a KP_E code.  About
+ * 0.1 s of device work on the context's stream; synchronises it.
+ */
+int kp_calibrate(kp_ctx* ctx, int32_t force, double* model_host);
+
 /* Copy the (tau_i, m_i) of the accepted substeps of the last call into host
  * arrays of capacity cap; returns the number copied (>= 0) or a KP_E code. */
 int kp_get_schedule(kp_ctx* ctx, double* tau_host, int32_t* m_host, int32_t cap);

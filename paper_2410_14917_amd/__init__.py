@@ -264,6 +264,17 @@ class Context:
         _lib.check(rc, self.h)
         return (outs, [r.as_dict() for r in inf]) if info else outs
 
+    def calibrate(self, force: bool = False):
+        """Measure (or read from KP_AUTOTUNE_CACHE) the batched planner's cost
+        model on this device; later batched calls of this context plan with
+        it.  Returns (source: "measured" | "cache", model dict)."""
+        import numpy as np
+        v = np.zeros(5)
+        rc = _lib.check(self.lib.kp_calibrate(self.h, int(bool(force)),
+                                              v.ctypes.data_as(ctypes.c_void_p)), self.h)
+        keys = ("bw_wg_Bps", "t_step_s", "t_team_s", "t_log_s", "t_expm64_s")
+        return ("cache" if rc == 1 else "measured"), dict(zip(keys, v.tolist()))
+
     def schedule(self, cap: int = 8192):
         import numpy as np
         tau = np.zeros(cap)

@@ -36,7 +36,7 @@ SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_c
            "kp_phi_combo_tangent",
            "kp_phi_combo_backward", "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
-           "kp_integrate",
+           "kp_integrate", "kp_calibrate",
            "kp_strerror", "kp_last_error", "kp_version", "kp_runtime_version")
 
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_arnoldi_step.argtypes = [P, I32]
     lib.kp_arnoldi_read.argtypes = [P, P, P, P, P, P]
     lib.kp_expm_hbar.argtypes = [P, P, I32, I32, D, P]
+    lib.kp_calibrate.argtypes = [P, I32, P]
     lib.kp_integrate.argtypes = [P, ctypes.POINTER(KpRhs), I32, D, I32, I32, P, D, I32,
                                  ctypes.POINTER(KpInfo)]
     lib.kp_strerror.argtypes = [ctypes.c_int]

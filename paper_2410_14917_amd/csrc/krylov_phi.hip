@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "kp_internal.h"
@@ -1990,6 +1991,223 @@ int kp_batch_plan(int32_t nprob, const kp_op* ops, const int32_t* p, const doubl
   if (makespan) *makespan = pl.makespan;
   if (work) *work = pl.work;
   return KP_OK;
+}
+
+// ---- calibration of the batched planner's cost model --------------------------
+
+namespace {
+
+// Solve the n x n system A x = b (row-major, n <= 8) by Gaussian elimination
+// with partial pivoting; false when singular.
+bool solve_small(int n, double* A, double* b, double* x) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+    std::swap(b[c], b[piv]);
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double v = b[r];
+    for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * x[k];
+    x[r] = v / A[r * n + r];
+  }
+  return true;
+}
+
+bool cache_read(const char* path, const std::string& key, kp::PlanModel* md) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[256];
+    double v[5];
+    if (std::sscanf(line, "%255s %lf %lf %lf %lf %lf", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 6 &&
+        key == k && v[0] > 0.0) {
+      md->bw_wg = v[0];
+      md->t_step = v[1];
+      md->t_team = v[2];
+      md->t_log = v[3];
+      md->t_expm64 = v[4];
+      found = true;   // the last entry of the key wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_write(const char* path, const std::string& key, const kp::PlanModel& md) {
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+      char k[256];
+      if (std::sscanf(line, "%255s", k) == 1 && key != k) keep.push_back(line);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto& l : keep) std::fputs(l.c_str(), f);
+  std::fprintf(f, "%s %.9g %.9g %.9g %.9g %.9g\n", key.c_str(), md.bw_wg, md.t_step, md.t_team,
+               md.t_log, md.t_expm64);
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+int kp_calibrate(kp_ctx* ctx, int32_t force, double* model_host) {
+  if (!ctx) return KP_EINVAL;
+  int rc = device_setup(ctx);
+  if (rc) return rc;
+  hipDeviceProp_t prop;
+  KP_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  char kbuf[256];
+  snprintf(kbuf, sizeof(kbuf), "%s/cu%d/lib%d", prop.gcnArchName, ctx->ncu, kp_version());
+  const std::string key(kbuf);
+  const char* path = std::getenv("KP_AUTOTUNE_CACHE");
+  kp::PlanModel md;
+  auto finish = [&](int code) {
+    ctx->model = md;
+    ctx->model_gen += 1;
+    if (model_host) {
+      model_host[0] = md.bw_wg;
+      model_host[1] = md.t_step;
+      model_host[2] = md.t_team;
+      model_host[3] = md.t_log;
+      model_host[4] = md.t_expm64;
+    }
+    return code;
+  };
+  if (!force && path && *path && cache_read(path, key, &md)) return finish(1);
+
+  // the small exponential at m = 64: device time of the test kernel
+  if (!ctx->st) {
+    KP_HIP(ctx, hipMalloc(&ctx->st, sizeof(State)));
+    KP_HIP(ctx, hipMalloc(&ctx->pub, sizeof(Pub)));
+    KP_HIP(ctx, hipMalloc(&ctx->sync, 64));
+    KP_HIP(ctx, hipMalloc(&ctx->ex, sizeof(double) * kp::kExSlots * kp::kNmPad * kp::kNmPad));
+    KP_HIP(ctx, hipMalloc(&ctx->tx, sizeof(double) * kp::kTailPad));
+  }
+  hipEvent_t e0, e1;
+  KP_HIP(ctx, hipEventCreate(&e0));
+  KP_HIP(ctx, hipEventCreate(&e1));
+  auto timed = [&](auto&& fn, int reps, double* med_s) -> int {
+    std::vector<float> ms;
+    for (int r = 0; r <= reps; ++r) {           // the first call warms up
+      KP_HIP(ctx, hipEventRecord(e0, ctx->stream));
+      const int c = fn();
+      if (c) return c;
+      KP_HIP(ctx, hipEventRecord(e1, ctx->stream));
+      KP_HIP(ctx, hipEventSynchronize(e1));
+      float t = 0.f;
+      KP_HIP(ctx, hipEventElapsedTime(&t, e0, e1));
+      if (r) ms.push_back(t);
+    }
+    std::sort(ms.begin(), ms.end());
+    *med_s = 1e-3 * ms[ms.size() / 2];
+    return KP_OK;
+  };
+  {
+    const int m = 64;
+    std::vector<double> Hs((size_t)kp::kLdh * kp::kMMax, 0.0);
+    for (int c = 0; c < m; ++c)
+      for (int r = 0; r <= c + 1; ++r)
+        Hs[(size_t)c * kp::kLdh + r] = (r == c) ? -2.0 - 0.05 * c : 0.3 * std::sin(1.0 + r + 7.0 * c);
+    KP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    KP_HIP(ctx, hipMemcpy(ctx->st->H, Hs.data(), Hs.size() * sizeof(double), hipMemcpyHostToDevice));
+    Args a{};
+    a.st = ctx->st;
+    a.ex = ctx->ex;
+    double t = 0.0;
+    rc = timed([&]() {
+      hipLaunchKernelGGL(kp::k_expm_test, dim3(1), dim3(kp::kThreads), 0, ctx->stream, a, m, 1.0);
+      return hipGetLastError() == hipSuccess ? KP_OK : KP_EHIP;
+    }, 5, &t);
+    if (rc) return rc;
+    md.t_expm64 = t;
+  }
+  // fixed-schedule solves (one substep of m steps, advection-diffusion, p = 1)
+  struct Cal { int nx, ny, rows, m; };
+  const Cal cals[] = {{1024, 1024, 0, 24}, {1024, 1024, 0, 8},  {2048, 1024, 0, 16},
+                      {64, 64, 0, 24},     {64, 64, 1, 24},     {256, 256, 16, 24},
+                      {512, 512, 8, 16}};
+  const int ncal = (int)(sizeof(cals) / sizeof(cals[0]));
+  const int p = 1;
+  const int64_t nmax = 2048 * 1024;
+  double* Bd = nullptr;
+  double* yd = nullptr;
+  KP_HIP(ctx, hipMalloc(&Bd, sizeof(double) * (size_t)nmax * (p + 1)));
+  if (hipMalloc(&yd, sizeof(double) * (size_t)nmax) != hipSuccess) {
+    hipFree(Bd);
+    return KP_ENOMEM;
+  }
+  hipLaunchKernelGGL(kp::k_fill_pattern, dim3(4096), dim3(256), 0, ctx->stream, Bd,
+                     (int64_t)nmax * (p + 1));
+  const kp_config saved = ctx->cfg;
+  double AtA[16] = {0}, Atb[4] = {0};
+  for (int i = 0; i < ncal && rc == KP_OK; ++i) {
+    const Cal& c = cals[i];
+    kp_op op{};
+    op.kind = KP_OP_ADR;
+    op.nx = c.nx;
+    op.ny = c.ny;
+    op.dx = 1.0 / c.nx;
+    op.dy = 1.0 / c.ny;
+    op.nu = 0.01;
+    op.ax = 1.0;
+    op.ay = 0.5;
+    op.brus_a = 1.0;
+    op.brus_b = 3.0;
+    ctx->cfg = saved;
+    ctx->cfg.orth = KP_ORTH_H_GSMGS;
+    ctx->cfg.basis_dtype = KP_BASIS_F64;
+    ctx->cfg.controller = KP_CTRL_POWER;
+    ctx->cfg.fixed_m = c.m;
+    ctx->cfg.fixed_substeps = 1;
+    ctx->cfg.rows_per_wg = c.rows;
+    const int64_t n = (int64_t)c.nx * c.ny;
+    double t = 0.0;
+    rc = timed([&]() { return kp_phi_combo(ctx, &op, Bd, p, n, 0.01, 1.0, c.m, yd, nullptr); },
+               3, &t);
+    if (rc) break;
+    const Args& a = ctx->last;             // the geometry of the timed call
+    const double g = a.nwg;
+    const double S = c.m;
+    const double P = S * (S + p + 0 + 6.0);
+    const double X = 8.0 * P * std::max((double)a.rows_per_wg * c.nx, md.e_min);
+    const double f[4] = {X, S, g > 1 ? S : 0.0, S * std::log2(g)};
+    const double y = t - md.t_expm64 * (S * S) / (64.0 * 64.0);
+    for (int r = 0; r < 4; ++r) {
+      Atb[r] += f[r] * y;
+      for (int k = 0; k < 4; ++k) AtA[r * 4 + k] += f[r] * f[k];
+    }
+  }
+  ctx->cfg = saved;
+  ctx->have_begin = 0;
+  hipFree(Bd);
+  hipFree(yd);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  double x[4] = {0, 0, 0, 0};
+  if (solve_small(4, AtA, Atb, x) && x[0] > 0.0) {
+    md.bw_wg = 1.0 / x[0];
+    md.t_step = std::max(x[1], 1e-7);
+    md.t_team = std::max(x[2], 0.0);
+    md.t_log = std::max(x[3], 0.0);
+  }
+  if (path && *path) cache_write(path, key, md);
+  return finish(0);
 }
 
 int kp_expm_hbar(kp_ctx* ctx, const double* H_host, int32_t ldh, int32_t m, double tau,

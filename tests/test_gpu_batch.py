@@ -228,3 +228,31 @@ def test_batched_fp32_basis():
         say(f"  fp32 batched kind={pr.op.kind} {pr.op.nx}x{pr.op.ny}: rel err {e:.2e}")
         assert inf["status"] == 0 and inf["t_end"] == pr.h
         assert e <= 1e-5
+
+
+def test_calibration_measures_caches_and_plans(tmp_path, monkeypatch):
+    """kp_calibrate: plausible measured constants, stored in and read back from
+    KP_AUTOTUNE_CACHE, forced re-measurement; a batched call planned with the
+    calibrated model gives the single calls' results."""
+    cache = tmp_path / "autotune.txt"
+    monkeypatch.setenv("KP_AUTOTUNE_CACHE", str(cache))
+    with kp.Context() as ctx:
+        src, md = ctx.calibrate()
+    print(src, md)
+    assert src == "measured" and cache.exists()
+    assert 1e9 < md["bw_wg_Bps"] < 1e12
+    assert 1e-7 <= md["t_step_s"] < 1e-3
+    assert 1e-6 < md["t_expm64_s"] < 1e-2
+    with kp.Context() as ctx:
+        src2, md2 = ctx.calibrate()
+        assert src2 == "cache" and md2 == pytest.approx(md, rel=1e-8)
+        src3, _ = ctx.calibrate(force=True)
+        assert src3 == "measured"
+        probs = [W.random_problem(400 + i, kind=W.OP_ADR, nx=32 + 17 * i, ny=24 + 9 * i, p=2,
+                                  h=0.05, nu=0.02, react=-0.2) for i in range(6)]
+        ops = [kp.Operator.from_host(q.op) for q in probs]
+        Bs = [torch.as_tensor(np.ascontiguousarray(q.B[:, :3].T), device="cuda") for q in probs]
+        ys = ctx.phi_combo_batched(ops, Bs, [q.h for q in probs], tol=1e-9, m_max=32)
+        for q, o, B, y in zip(probs, ops, Bs, ys):
+            y1 = ctx.phi_combo(o, B, q.h, tol=1e-9, m_max=32)
+            assert torch.linalg.vector_norm(y - y1) <= 1e-10 * torch.linalg.vector_norm(y1)
