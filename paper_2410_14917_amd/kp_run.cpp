@@ -190,6 +190,7 @@ int main(int argc, char** argv) {
               "\"rejected\": %d, \"arnoldi_steps\": %d, \"hip_runtime_version\": %d}\n",
               n, steps, mean, sorted[steps / 2], sorted.front(), sorted.back(), info.status,
               info.substeps, info.rejected, info.arnoldi_steps, rv);
+  std::fflush(stdout);  // a profiler may end the process abnormally at exit
   kp_destroy(ctx);
   hipFree(dB);
   hipFree(d0);
