@@ -434,8 +434,9 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
  * Small phi evaluation on its own, for tests: F = exp(tau * Hbar) e_1 with the
  * (m+1) x (m+1) matrix Hbar = [[H_m, 0], [h_{m+1,m} e_m^T, 0]] read from the
  * host array H_host ((m+1) x m column-major, leading dimension ldh >= m+1).
- * Runs the device's Pade [13/13] scaling-and-squaring routine in one
- * workgroup and copies F (m+1 doubles) to F_host.
+ * Runs the device's small-exponential routine (degree-19 Taylor polynomial
+ * with scaling and squaring) in one workgroup and copies F (m+1 doubles) to
+ * F_host.
  */
 int kp_expm_hbar(kp_ctx* ctx, const double* H_host, int32_t ldh, int32_t m,
                  double tau, double* F_host);

@@ -7,8 +7,9 @@ definition by parts.
 
 The dense exponential is a Taylor series with scaling and squaring: the matrix
 is scaled by 2^-s until its 1-norm is at most 1/2, the series is summed until
-the terms stop contributing, and the result is squared s times.  (The GPU uses
-a Pade approximant instead; the two methods share nothing.)
+the terms stop contributing, and the result is squared s times.  (The GPU
+evaluates a fixed-degree polynomial by a different scheme and scaling; the two
+share no code.)
 
 The phi combination sum_k h^k phi_k(hA) b_k is defined here as the top block of
 exp(h * Atilde) [b_0; e_p] with Atilde = [[A, B], [0, K]], B = [b_p, ..., b_1],

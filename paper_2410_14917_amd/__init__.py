@@ -346,7 +346,8 @@ class Context:
         return (u, inf.as_dict()) if info else u
 
     def expm_hbar(self, H, m: int, tau: float):
-        """exp(tau Hbar) e_1 by the device's Pade routine; H is (m+1) x m."""
+        """exp(tau Hbar) e_1 by the device's small-exponential routine; H is
+        (m+1) x m."""
         import numpy as np
         Hf = np.asfortranarray(np.asarray(H, dtype=np.float64)[:m + 1, :m])
         F = np.zeros(m + 1)

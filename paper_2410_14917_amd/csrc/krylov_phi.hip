@@ -49,7 +49,7 @@ constexpr int kLdsDoubles = (2 * kNmPad * kNmPad > kOffHl + kHaloCap) ? 2 * kNmP
 static_assert(kOffGrp + kRg * kKStride <= kOffCoef, "grp overlaps coef");
 static_assert(kOffWk + kWkDoubles <= kOffCoef, "wk overlaps coef");
 static_assert(kOffOwn + kKStride <= kOffHl, "tv / own overlap the halo copy");
-static_assert(kLdsDoubles >= kNmPad * kGjLd, "the small exponential does not fit the phase buffer");
+static_assert(kLdsDoubles >= 2 * kNmPad * kNmPad, "the small exponential does not fit the phase buffer");
 
 // One phase of the call for this workgroup.  MS: the kernel also runs the
 // processes with one reduction per inner product (MGS) or per window

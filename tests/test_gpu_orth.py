@@ -111,7 +111,9 @@ def test_phi_combo_fixed_schedule(case, orth, oorth):
     assert info["status"] == 0
     assert info["substeps"] == nsub and info["arnoldi_steps"] == rinfo.arnoldi_steps
     assert rel(y.cpu().numpy(), ref) <= FP64_TOL
-    assert info["err_max"] == pytest.approx(rinfo.err_max, rel=1e-6, abs=1e-300)
+    # (an estimate far below u ||F|| agrees only to that absolute level)
+    assert info["err_max"] == pytest.approx(rinfo.err_max, rel=1e-6,
+                                            abs=1e-15 * float(np.abs(ref).max()))
 
 
 ADAPT = [

@@ -44,7 +44,7 @@ def _krylov_H(kind, m, seed):
 
 @pytest.mark.parametrize("m", [1, 2, 7, 16, 40, 64])
 @pytest.mark.parametrize("tau", [1e-4, 0.01, 0.05, 0.2])
-def test_expm_pade_matches_oracle_taylor(m, tau):
+def test_expm_matches_oracle_taylor(m, tau):
     say(f"expm m={m} tau={tau}")
     H = _krylov_H(W.OP_ADR, m, 100 + m)
     with kp.Context() as ctx:
@@ -136,7 +136,11 @@ def test_phi_combo_fixed_schedule(case, orth):
     assert info["substeps"] == nsub and info["arnoldi_steps"] == rinfo.arnoldi_steps
     assert [s[1] for s in sched] == [s[1] for s in rinfo.schedule]
     assert rel(y.cpu().numpy(), ref) <= FP64_TOL
-    assert info["err_max"] == pytest.approx(rinfo.err_max, rel=1e-6, abs=1e-300)
+    # the estimate beta |F_m| is an entry of the small exponential: where it
+    # lies far below u ||F|| (no accuracy request here) the two exponential
+    # methods agree only to that absolute level, relative to the solution
+    assert info["err_max"] == pytest.approx(rinfo.err_max, rel=1e-6,
+                                            abs=1e-15 * float(np.abs(ref).max()))
 
 
 def test_config1_matches_dft_closed_form():
