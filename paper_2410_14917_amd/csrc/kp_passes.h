@@ -157,30 +157,69 @@ __device__ inline void tile_pairs(int64_t q0, int64_t pend, uint32_t* lo, bool* 
   }
 }
 
-// acc[r] += sum over the C columns i = i0, i0 + step, ... of coef[i] V_i(pair r).
-// All C * kR loads are issued before the first multiply-add.
-// The coefficients are read with coherent loads (they were published by the
-// leader), issued together with the column loads.
+// Columns of one chunk are held as loaded (a float basis stays packed until
+// it is multiplied), so that a float chunk of 2 * kCh columns takes the
+// registers of a double chunk of kCh: the float pass keeps as many bytes in
+// flight as the double one.  Each column's sums are formed and recorded on
+// their own, so the chunk width does not change any result.
+template <typename TB> struct Raw;
+template <> struct Raw<double> {
+  typedef double2 type;
+  static constexpr int kCols = kCh;
+  __device__ static double2 load(const double* base, uint32_t byte_off) {
+    return load_at(base, byte_off);
+  }
+};
+template <> struct Raw<float> {
+  typedef kp_f2 type;
+  static constexpr int kCols = 2 * kCh;
+  __device__ static kp_f2 load(const float* base, uint32_t byte_off) {
+    return *(const KP_GLOBAL kp_f2*)((const KP_GLOBAL char*)base + byte_off);
+  }
+};
+
+// acc[r] += sum over the nc columns i = i0, i0 + step, ... of coef[i] V_i(pair r),
+// the columns in that order; nc <= C is wave-uniform.  The loads are kept as
+// stored (float pairs stay packed) and widened at use.  The columns past nc
+// add nothing: a double chunk loads them as repeats of the last column with
+// coefficient 0, so that all C * kR loads issue before the first multiply-add
+// without a branch; a float chunk skips them behind a uniform branch (measured
+// faster for each type: 2 % and 1 % of the benchmark calls against
+// single-column remainder steps).  The coefficients are read with coherent
+// loads (they were published by the leader), issued with the column loads.
 template <typename TB, int C>
-__device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, int step,
+__device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, int step, int nc,
                                  const double* coef, const uint32_t* lo, double2* acc) {
-  double2 v[C][kR];
+  typename Raw<TB>::type v[C][kR];
   double ci[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const TB* vc = uniform_ptr(V + (int64_t)(i0 + c * step) * ld + t0);
-    ci[c] = cload(coef + i0 + c * step);
+    const int i = i0 + min(c, nc - 1) * step;
+    const TB* vc = uniform_ptr(V + (int64_t)i * ld + t0);
+    if constexpr (sizeof(TB) == 8) {
+      const double cv = cload(coef + i);
+      ci[c] = (c < nc) ? cv : 0.0;
 #pragma unroll
-    for (int r = 0; r < kR; ++r) v[c][r] = load_at(vc, lo[r] * (uint32_t)sizeof(TB));
+      for (int r = 0; r < kR; ++r) v[c][r] = Raw<TB>::load(vc, lo[r] * (uint32_t)sizeof(TB));
+    } else if (c < nc) {
+      ci[c] = cload(coef + i);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) v[c][r] = Raw<TB>::load(vc, lo[r] * (uint32_t)sizeof(TB));
+    } else {
+      ci[c] = 0.0;
+#pragma unroll
+      for (int r = 0; r < kR; ++r) v[c][r] = typename Raw<TB>::type{};
+    }
   }
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-      acc[r].x += ci[c] * v[c][r].x;
-      acc[r].y += ci[c] * v[c][r].y;
+      acc[r].x += ci[c] * (double)v[c][r].x;
+      acc[r].y += ci[c] * (double)v[c][r].y;
     }
 }
+
 
 // Index of the halo slot of (workgroup w, plane s, side: 0 first row, 1 last row).
 __device__ inline int64_t halo_at(const Args& a, int w, int s, int side, int ix) {
@@ -525,26 +564,6 @@ __device__ __attribute__((always_inline)) inline void stage_pass(const Args& a, 
 // basis, 2 * kCh of a float one), software-pipelined: the loads of the next
 // chunk are in flight while the wave reduces the current one.
 
-// Columns of one chunk are held as loaded (a float basis stays packed until
-// it is multiplied), so that a float chunk of 2 * kCh columns takes the
-// registers of a double chunk of kCh: the float pass keeps as many bytes in
-// flight as the double one.  Each column's sums are formed and recorded on
-// their own, so the chunk width does not change any result.
-template <typename TB> struct Raw;
-template <> struct Raw<double> {
-  typedef double2 type;
-  static constexpr int kCols = kCh;
-  __device__ static double2 load(const double* base, uint32_t byte_off) {
-    return load_at(base, byte_off);
-  }
-};
-template <> struct Raw<float> {
-  typedef kp_f2 type;
-  static constexpr int kCols = 2 * kCh;
-  __device__ static kp_f2 load(const float* base, uint32_t byte_off) {
-    return *(const KP_GLOBAL kp_f2*)((const KP_GLOBAL char*)base + byte_off);
-  }
-};
 
 // Per-wave sums of x_i . x and x_i . w for the C columns of one chunk
 // (columns past nc repeat the last one and are not recorded).
@@ -706,9 +725,8 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
         const double2 w = Pair<TB>::load(wcol + t0 + lo[r]);
         acc[r] = make_double2(cw * w.x, cw * w.y);
       }
-      int i1 = jj;
-      for (; i1 >= kCu - 1; i1 -= kCu) axpy_cols<TB, kCu>(V, ld, t0, i1, -1, coef, lo, acc);
-      for (; i1 >= 0; --i1) axpy_cols<TB, 1>(V, ld, t0, i1, -1, coef, lo, acc);
+      for (int i1 = jj; i1 >= 0; i1 -= kCu)
+        axpy_cols<TB, kCu>(V, ld, t0, i1, -1, min(kCu, i1 + 1), coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
@@ -749,9 +767,8 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
       double2 acc[kR];
 #pragma unroll
       for (int r = 0; r < kR; ++r) acc[r] = make_double2(0.0, 0.0);
-      int i0 = 0;
-      for (; i0 + kCu <= m; i0 += kCu) axpy_cols<TB, kCu>(V, ld, t0, i0, 1, coef, lo, acc);
-      for (; i0 < m; ++i0) axpy_cols<TB, 1>(V, ld, t0, i0, 1, coef, lo, acc);
+      for (int i0 = 0; i0 < m; i0 += kCu)
+        axpy_cols<TB, kCu>(V, ld, t0, i0, 1, min(kCu, m - i0), coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         if (ok[r]) {
@@ -922,7 +939,7 @@ __device__ __attribute__((always_inline)) inline void proj_pass(const Args& a, i
         acc[r] = load_at(wc, lo[r] * (uint32_t)sizeof(TB));
         dv[r] = (dcol >= 0) ? load_at(dc, lo[r] * (uint32_t)sizeof(TB)) : make_double2(0.0, 0.0);
       }
-      for (int c = ca; c <= cb; ++c) axpy_cols<TB, 1>(V, ld, t0, c, 1, coef, lo, acc);
+      for (int c = ca; c <= cb; ++c) axpy_cols<TB, 1>(V, ld, t0, c, 1, 1, coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
