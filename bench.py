@@ -1,14 +1,15 @@
 """Benchmark of the Krylov phi combination on one MI355X.
 
 One timed step = one full phi_combo call (stage, hybrid low-synchronisation
-Arnoldi, small Pade exponential, on-device substep controller, combine) on the
+Arnoldi, small exponential, on-device substep controller, combine) on the
 Allen-Cahn Jacobian workload: A = 0.01 Lap + diag(1 - 3u^2) on a 1024 x 1024
 periodic grid (N = 1,048,576), p = 2, h = 0.1, tol = 1e-8, m <= 64, H-GSMGS.
 The whole call is one cooperative kernel launch.
 
 Printed: one JSON line with Arnoldi steps/s (whole job), phi_combo/s, the
 roofline of the persistent kernel (algorithmic HBM bytes per launch over its
-average duration, HIP events on the launch stream), the call's error against
+average duration, HIP events on the launch stream; also against the rate a
+plain streaming read reaches on the same device), the call's error against
 the float64 CPU oracle replaying its schedule, and legs:
 
   fixed_m64   one substep of exactly 64 Arnoldi steps per orthogonalisation
@@ -25,6 +26,10 @@ the float64 CPU oracle replaying its schedule, and legs:
   integrators EPI4, EPI5, SRERK3 (Section 4.1) on the Allen-Cahn and ADR
               problems at 2000^2, time to solution with H-GSMGS and ioCGS
   cpu_baseline  the oracle timed on the host cores (1 thread and all)
+
+--timeline DIR records the per-phase device timeline of the benchmark call
+(the timeline build of the library) instead; --dump DIR writes the workload
+arrays for the native runner.
 """
 from __future__ import annotations
 
@@ -245,6 +250,111 @@ def time_launches(torch, stream, fn, nrep):
     return [a.elapsed_time(b) for a, b in zip(e0, e1)]
 
 
+def timeline_summary(T, rate=100e6):
+    """Per-phase breakdown of one call from its device timeline T (phases x
+    workgroups x 8 int64 clock stamps, the layout kp_set_timeline documents;
+    workgroup 0 leads; the workgroups that own rows are those that stamp an
+    update).  Times in microseconds.  An Arnoldi step k (with an update) is
+    measured from the previous phase's release (t0): the median workgroup's
+    release seen, update done, halo flags seen and arrival, the last
+    arrival, the leader's reduction after the last arrival, its serial step
+    and release, and the whole step (release to release).  Other phases:
+    count and mean duration by kind.  Also the least-squares line of the
+    step duration in the step index j."""
+    import numpy as np
+    T = np.asarray(T, dtype=np.float64)
+    us = 1e6 / rate
+    live = [k for k in range(T.shape[0]) if T[k, 0, 0] > 0]
+    names = {0: "start", 1: "arnoldi_step", 2: "close", 3: "small_exponential",
+             4: "combine", 5: "finish", 7: "mgs_matvec", 8: "mgs_projection"}
+    # workgroups that own rows: they stamp an update in some phase (the others
+    # of the grid only meet the barriers)
+    owners = np.nonzero(T[live, :, 1].max(axis=0) > 0)[0]
+    others = owners[owners > 0]
+    steps, other = [], {}
+    for a, b in zip(live[:-1], live[1:]):
+        code = int(T[b, 0, 4])
+        ph, j = code // 1000, code % 1000
+        t0 = T[a, 0, 7]
+        dur = (T[b, 0, 7] - t0) * us
+        w = T[b, others]
+        if ph == 1 and j >= 1 and len(others) and w[:, 1].min() > 0:
+            arr = T[b, owners, 3]
+            steps.append([j, dur,
+                          (np.median(w[:, 0]) - t0) * us,
+                          (np.median(w[:, 1]) - t0) * us,
+                          (np.median(w[:, 2]) - t0) * us,
+                          (np.median(w[:, 3]) - t0) * us,
+                          (arr.max() - t0) * us,
+                          (T[b, 0, 5] - arr.max()) * us,
+                          (T[b, 0, 6] - T[b, 0, 5]) * us,
+                          (T[b, 0, 7] - T[b, 0, 6]) * us])
+        else:
+            other.setdefault(names.get(ph, str(ph)), []).append(dur)
+    cols = ["j", "step_us", "release_seen_us", "update_done_us", "halo_flags_us",
+            "arrival_median_us", "arrival_last_us", "reduction_after_last_us",
+            "serial_us", "release_us"]
+    out = {"arnoldi_steps": len(steps)}
+    if steps:
+        S = np.array(steps)
+        out["step_mean_us"] = {c: round(float(S[:, i].mean()), 2) for i, c in enumerate(cols)
+                               if i > 0}
+        slope, icpt = np.polyfit(S[:, 0], S[:, 1], 1)
+        out["step_fit_us"] = {"intercept": round(float(icpt), 2), "per_j": round(float(slope), 3)}
+        out["steps_total_ms"] = round(float(S[:, 1].sum()) / 1e3, 3)
+        out["rows"] = {"columns": cols, "values": S.round(3).tolist()}
+    out["other_phases"] = {k: {"count": len(v), "mean_us": round(float(np.mean(v)), 1),
+                               "total_ms": round(float(np.sum(v)) / 1e3, 3)}
+                           for k, v in other.items()}
+    return out
+
+
+def run_timeline(outdir, side=1024):
+    """Record the device timeline of the benchmark call and of one fixed
+    m = 64 substep with the timeline build of the library; write the raw
+    stamps (.npy) and the summaries (.json) to outdir and print the
+    summaries without their per-step rows."""
+    import numpy as np
+    from paper_2410_14917_amd import _lib
+    lib = _lib.load(_lib.TIMELINE_LIB_PATH)        # before anything loads the default build
+    import ctypes
+    import torch
+    import workloads as W
+    import paper_2410_14917_amd as kp
+    slots, wgs = ctypes.c_int32(), ctypes.c_int32()
+    if lib.kp_timeline_layout(ctypes.byref(slots), ctypes.byref(wgs)) != 1:
+        raise RuntimeError("the loaded library does not record timelines")
+    os.makedirs(outdir, exist_ok=True)
+    pr = W.config2(side=side)
+    op = kp.Operator.from_host(pr.op)
+    B = torch.as_tensor(np.ascontiguousarray(pr.B.T), device="cuda")
+    out = torch.empty(pr.op.n, dtype=torch.float64, device="cuda")
+    kmax = 4096
+    ts = torch.zeros(kmax * wgs.value * slots.value, dtype=torch.int64, device="cuda")
+    result = {}
+    for label, kw in (("adaptive", {}), ("fixed_m64", dict(fixed_m=64, fixed_substeps=1))):
+        with kp.Context(**kw) as ctx:
+            ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=64, out=out)
+            ts.zero_()
+            _lib.check(lib.kp_set_timeline(ctx.h, ctypes.c_void_p(ts.data_ptr()), kmax), ctx.h)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, info = ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=64, out=out, info=True)
+            e1.record()
+            torch.cuda.synchronize()
+            _lib.check(lib.kp_set_timeline(ctx.h, None, 0), ctx.h)
+        T = ts.cpu().numpy().reshape(kmax, wgs.value, slots.value)
+        used = int(np.nonzero(T[:, 0, 0])[0].max()) + 1
+        np.save(os.path.join(outdir, f"timeline_{label}.npy"), T[:used])
+        summ = timeline_summary(T[:used])
+        summ["event_ms"] = round(e0.elapsed_time(e1), 3)
+        summ["info"] = info
+        with open(os.path.join(outdir, f"timeline_{label}.json"), "w") as f:
+            json.dump(summ, f)
+        result[label] = {k: v for k, v in summ.items() if k != "rows"}
+    print(json.dumps(result, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,9 +381,15 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--dump", metavar="DIR",
                     help="only write the workload arrays and kp_run arguments to DIR")
+    ap.add_argument("--timeline", metavar="DIR",
+                    help="only record the per-phase device timeline of the benchmark call "
+                         "(timeline build of the library) into DIR")
     args = ap.parse_args()
     if args.dump:
         dump_inputs(args.dump)
+        return
+    if args.timeline:
+        run_timeline(args.timeline, side=args.side)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -328,6 +444,9 @@ def main():
     vec = vectors_per_call(sched, p, c_fields, args.orth)
     bytes_per_call = vec * 8.0 * N
     achieved = bytes_per_call / (avg_ms * 1e-3) / 1e9
+    # what a plain streaming read reaches on this device (1 GiB, same launch shape)
+    read_ceiling = ctx.read_bandwidth(1 << 30, 20)
+    log(f"plain streaming read: {read_ceiling:.1f} GB/s")
     log(f"{args.steps} calls: wall {wall:.3f}s, event avg {avg_ms:.3f} ms/launch, "
         f"{vec} vector passes/call")
     assert np.array_equal(out.cpu().numpy(), y_main), "repeated calls differ"
@@ -361,7 +480,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if args.orth == "h-gsmgs" else None,
                      "kernel": KERNEL,
-                     "bytes_per_launch": bytes_per_call, "avg_launch_ms": round(avg_ms, 4)},
+                     "bytes_per_launch": bytes_per_call, "avg_launch_ms": round(avg_ms, 4),
+                     "read_ceiling_GBps": round(read_ceiling, 1),
+                     "frac_of_read_ceiling": round(achieved / read_ceiling, 4)},
         "runtime": kp.runtime_info(),
     }
 

@@ -441,6 +441,41 @@ int kp_arnoldi_read(kp_ctx* ctx, double* H_host, double* V_host, int32_t* j_host
 int kp_expm_hbar(kp_ctx* ctx, const double* H_host, int32_t ldh, int32_t m,
                  double tau, double* F_host);
 
+/*
+ * Practical HBM read rate, for reporting a kernel's bandwidth against what
+ * streaming reads reach (diagnostic; allocates and frees a buffer of `bytes`
+ * device bytes, 1 MiB..64 GiB).  One workgroup of 512 threads per compute
+ * unit, the persistent kernels' launch shape, reads the buffer with 16-byte
+ * loads, four in flight per thread; *gbps_host = bytes / median time of
+ * `reps` (1..1000) launches after one warm-up, in GB/s (1e9 B/s).  On the
+ * context's stream; synchronises it.
+ */
+int kp_read_bandwidth(kp_ctx* ctx, int64_t bytes, int32_t reps, double* gbps_host);
+
+/*
+ * Device timeline of single calls, for profiling (the library built with
+ * KP_TIMELINE, libkrylov_phi_timeline.so; the default build returns
+ * KP_EUNSUPPORTED and records nothing).  During every later kp_phi_combo on
+ * ctx, thread 0 of each workgroup w < workgroups (kp_timeline_layout) stores
+ * the GPU's 100 MHz constant clock at fixed points of phase k < kmax into
+ * ts[(k * workgroups + w) * slots + slot] (device memory, int64, owned by
+ * the caller, at least kmax * workgroups * slots entries; entries that no
+ * workgroup reaches keep their value).  Slots: 0 phase start; 1 the basis
+ * update done and its stores complete; 2 the neighbours' halo flags seen;
+ * 3 the streaming part done; 4 the release seen (workgroup 0: the phase
+ * code phase * 1000 + j, phases numbered as in the kernel: 0 start vector,
+ * 1 Arnoldi step, 2 close, 3 small exponential, 4 combination, 5 finish,
+ * 7 and 8 matvec and projection of MGS / ioCGS); 5 workgroup 0's reduction
+ * done; 6 its serial work done; 7 its release published.  The points sit at
+ * existing barriers, so recording adds no synchronisation.  kmax = 0 stops
+ * recording.
+ */
+int kp_set_timeline(kp_ctx* ctx, long long* ts, int32_t kmax);
+
+/* Slots per workgroup and workgroups of the timeline layout; returns 1 when
+ * the library records timelines (KP_TIMELINE build), else 0. */
+int kp_timeline_layout(int32_t* slots_host, int32_t* workgroups_host);
+
 /* Static description of a return code. */
 const char* kp_strerror(int code);
 

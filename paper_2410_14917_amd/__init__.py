@@ -275,6 +275,14 @@ class Context:
         keys = ("bw_wg_Bps", "t_step_s", "t_team_s", "t_log_s", "t_expm64_s")
         return ("cache" if rc == 1 else "measured"), dict(zip(keys, v.tolist()))
 
+    def read_bandwidth(self, nbytes: int = 1 << 30, reps: int = 20) -> float:
+        """Practical HBM read rate in GB/s (kp_read_bandwidth: a plain
+        streaming read in the persistent kernels' launch shape)."""
+        v = ctypes.c_double()
+        _lib.check(self.lib.kp_read_bandwidth(self.h, int(nbytes), int(reps), ctypes.byref(v)),
+                   self.h)
+        return v.value
+
     def schedule(self, cap: int = 8192):
         import numpy as np
         tau = np.zeros(cap)

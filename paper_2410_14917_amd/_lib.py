@@ -11,6 +11,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkrylov_phi.so")
+TIMELINE_LIB_PATH = os.path.join(HERE, "libkrylov_phi_timeline.so")   # profiling build
 
 # ---- constants (mirror include/krylov_phi.h) --------------------------------
 KP_OK, KP_EINVAL, KP_ENOMEM, KP_EHIP, KP_EUNSUPPORTED, KP_ESTATE, KP_ETOOLARGE = \
@@ -37,7 +38,8 @@ SYMBOLS = ("kp_create", "kp_destroy", "kp_set_config", "kp_phi_combo", "kp_phi_c
            "kp_phi_combo_backward", "kp_phi_combo_batched", "kp_get_batch_schedule", "kp_batch_plan", "kp_get_schedule",
            "kp_arnoldi_begin", "kp_arnoldi_step", "kp_arnoldi_read", "kp_expm_hbar",
            "kp_integrate", "kp_calibrate",
-           "kp_strerror", "kp_last_error", "kp_version", "kp_runtime_version")
+           "kp_strerror", "kp_last_error", "kp_version", "kp_runtime_version",
+           "kp_set_timeline", "kp_timeline_layout", "kp_read_bandwidth")
 
 
 class KpOp(ctypes.Structure):
@@ -132,6 +134,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kp_last_error.restype = ctypes.c_char_p
     lib.kp_version.argtypes = []
     lib.kp_runtime_version.argtypes = [P, P]
+    lib.kp_set_timeline.argtypes = [P, P, I32]
+    lib.kp_timeline_layout.argtypes = [P, P]
+    lib.kp_read_bandwidth.argtypes = [P, I64, I32, P]
     for name in SYMBOLS:
         fn = getattr(lib, name)
         if fn.restype is None and name not in ("kp_strerror", "kp_last_error"):

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "krylov_phi.hip")
 OUT = os.path.join(HERE, "libkrylov_phi.so")
+TIMELINE_OUT = os.path.join(HERE, "libkrylov_phi_timeline.so")
 CLIENT_SRC = os.path.join(ROOT, "tests", "c_abi_client.cpp")
 CLIENT = os.path.join(ROOT, "tests", "c_abi_client")
 RUNNER_SRC = os.path.join(HERE, "kp_run.cpp")
@@ -31,9 +32,25 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, OUT)
+    build_timeline(verbose)
     build_client(verbose)
     build_runner(verbose)
     return OUT
+
+
+def build_timeline(verbose: bool = False) -> str:
+    """The same library with the device timeline compiled in (KP_TIMELINE:
+    kp_set_timeline records per-phase clock stamps), for profiling only."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = TIMELINE_OUT + ".tmp"
+    cmd = [hipcc, *FLAGS, "-DKP_TIMELINE", SRC, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc (timeline build) failed:\n" + res.stdout + res.stderr)
+    if verbose:
+        print(" ".join(cmd))
+    os.replace(tmp, TIMELINE_OUT)
+    return TIMELINE_OUT
 
 
 def build_runner(verbose: bool = False) -> str:

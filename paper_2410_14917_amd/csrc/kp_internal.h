@@ -159,6 +159,10 @@ struct Args {
   int stop_j;         // pause when this many steps are completed (INT_MAX: never)
   int basis_f32;
   int halo_lds;       // the stencil halo rows fit the LDS copy of the matvec
+#ifdef KP_TIMELINE
+  long long* ts;      // device timeline (see KP_TS), null when not recording
+  int ts_kmax;        // phases the timeline holds
+#endif
   double inv_nx;      // 1 / nx (row of an in-plane index, corrected exactly)
   double h, tol, delta, eps_bd;
   int64_t wait_ticks; // bound of a grid-wide wait, steady-counter ticks
@@ -294,6 +298,27 @@ __device__ inline unsigned long long* release_word(const Args& a) {
 
 __device__ inline void wait_all_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
+// Device timeline, compiled in with KP_TIMELINE only (a separate build of the
+// library): thread 0 of workgroup w < kTsWgs stores the 100 MHz constant clock
+// at fixed points of phase k into ts[(k * kTsWgs + w) * kTsSlots + slot], at
+// existing barriers, so the recording adds no synchronisation.  Slots: 0
+// phase start; 1 update done and its stores complete; 2 neighbours' halo
+// flags seen; 3 streaming part done; 4 release seen (workgroup 0: the phase
+// code, phase * 1000 + j); 5 workgroup 0's reduction done; 6 its serial work
+// done; 7 its release published.
+constexpr int kTsSlots = 8, kTsWgs = 256;
+#ifdef KP_TIMELINE
+#define KP_TSV(a, k, slot, v)                                                             \
+  do {                                                                                    \
+    if ((a).ts && (int)(k) < (a).ts_kmax && wg_rank(a) < kTsWgs && kp_tid() == 0)         \
+      (a).ts[((int64_t)(k) * kTsWgs + wg_rank(a)) * kTsSlots + (slot)] = (long long)(v);  \
+  } while (0)
+#define KP_TS(a, k, slot) KP_TSV(a, k, slot, wall_clock64())
+#else
+#define KP_TSV(a, k, slot, v) ((void)0)
+#define KP_TS(a, k, slot) ((void)0)
+#endif
+
 __device__ inline bool aborted(const Args& a) { return cload(a.sync + kSyncAbort) != 0u; }
 
 __device__ inline bool wait_expired(const Args& a, int64_t t0) {
@@ -393,6 +418,7 @@ __device__ inline void bar_wait(const Args& a, unsigned k, Ctl* cur, int* ok) {
 __device__ inline void flag_publish(const Args& a, unsigned k) {
   wait_all_stores();
   __syncthreads();
+  KP_TS(a, k, 1);
   if (kp_tid() == 0) cstore(a.flags + (int64_t)wg_rank(a) * kFlagStride, k);
 }
 
@@ -414,6 +440,7 @@ __device__ inline void flag_wait_neighbours(const Args& a, unsigned k) {
     }
   }
   __syncthreads();
+  KP_TS(a, k, 2);
 }
 
 }  // namespace kp

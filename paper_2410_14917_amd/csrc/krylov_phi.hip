@@ -69,6 +69,8 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
   double* hl = lds + kOffHl;
   const bool lead = wg_rank(a) == 0;
   const Ctl c = cur;
+  KP_TS(a, k, 0);
+  if (lead) KP_TSV(a, k, 4, c.phase * 1000 + c.j);
   // this workgroup's row of the step buffer of barrier k + 1 is free again
   // (consumed at barrier k - 1): mark it unwritten before anything of this
   // phase is stored
@@ -135,6 +137,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     default:
       break;
   }
+  KP_TS(a, k, 3);
   // (the leader counts its arrival at a step barrier after the release, so
   // that the atomic is not outstanding while it polls)
   if (c.phase != PH_STEP)
@@ -143,6 +146,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     bar_count(a);
   if (!lead) {
     bar_wait(a, k, &cur, &ok);
+    KP_TS(a, k, 4);
     return;
   }
   // serial part (workgroup 0)
@@ -158,6 +162,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     case PH_STEP:
       gather_step_partials(a, step_part(a, k), 2 * c.j + 3, own, tv, grp, &ok);
       if (!ok) return;
+      KP_TS(a, k, 5);
       scalar_step(a, c.j, tv, L, wk, nxt);
       break;
     case PH_CLOSE:
@@ -188,7 +193,9 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     default:
       break;
   }
+  KP_TS(a, k, 6);
   bar_release(a, k, nxt, a.pub);
+  KP_TS(a, k, 7);
   if (c.phase == PH_STEP) bar_count(a);
   if (kp_tid() == 0) cur = nxt;
 }
@@ -624,6 +631,22 @@ __global__ __launch_bounds__(256) void k_fill_pattern(double* x, int64_t n) {
     x[e] = sin(0.37 * (double)(e + 1)) + 0.5 * cos(0.0101 * (double)e);
 }
 
+// Plain streaming read (kp_read_bandwidth): each thread sums its 16-byte
+// elements of x, four loads in flight per round, and one lane per wave
+// stores its sum (so the loads are not dead); the practical HBM read rate.
+__global__ __launch_bounds__(kThreads) void k_read_probe(const double2* x, int64_t n2,
+                                                         double* sink) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double s = 0.0;
+  for (; e + 3 * stride < n2; e += 4 * stride) {
+    const double2 v0 = x[e], v1 = x[e + stride], v2 = x[e + 2 * stride], v3 = x[e + 3 * stride];
+    s += (v0.x + v0.y) + (v1.x + v1.y) + (v2.x + v2.y) + (v3.x + v3.y);
+  }
+  for (; e < n2; e += stride) s += x[e].x + x[e].y;
+  if ((threadIdx.x & 63) == 0) sink[(int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)] = s;
+}
+
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
   __shared__ double lds[kLdsDoubles];
@@ -682,6 +705,8 @@ struct kp_ctx {
   State* st_last = nullptr;      // State of the last single call
   kp::PlanModel model;           // the batched planner's cost model (kp_calibrate)
   int model_gen = 0;             // bumped when the model changes (part of the plan key)
+  long long* ts = nullptr;       // device timeline of single calls (KP_TIMELINE builds)
+  int ts_kmax = 0;
   char err[512] = {0};
 };
 
@@ -922,6 +947,10 @@ int prepare(kp_ctx* ctx, Args* a) {
   a->pub = ctx->pub;
   a->ex = ctx->ex;
   a->wait_ticks = ctx->wait_ticks;
+#ifdef KP_TIMELINE
+  a->ts = ctx->ts;
+  a->ts_kmax = ctx->ts_kmax;
+#endif
   return KP_OK;
 }
 
@@ -1340,6 +1369,75 @@ void batch_fill_args(BatchCache* b, const std::vector<Args>& as, int64_t wait_ti
 extern "C" {
 
 int kp_version(void) { return 10300; }
+
+int kp_read_bandwidth(kp_ctx* ctx, int64_t bytes, int32_t reps, double* gbps_host) {
+  if (!ctx || !gbps_host || reps < 1 || reps > 1000 || bytes < (int64_t)1 << 20 ||
+      bytes > (int64_t)1 << 36)
+    return KP_EINVAL;
+  int rc = device_setup(ctx);
+  if (rc) return rc;
+  const int64_t n2 = bytes / 16;
+  const int nblk = ctx->ncu;                       // the persistent kernels' launch shape
+  double2* x = nullptr;
+  double* sink = nullptr;
+  if (hipMalloc(&x, (size_t)n2 * 16) != hipSuccess) return KP_ENOMEM;
+  if (hipMalloc(&sink, sizeof(double) * (size_t)nblk * (kp::kThreads / 64)) != hipSuccess) {
+    hipFree(x);
+    return KP_ENOMEM;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<float> ms;
+  rc = KP_OK;
+  hipLaunchKernelGGL(kp::k_zero, dim3(4096), dim3(256), 0, ctx->stream, (double*)x, 2 * n2);
+  if (hipGetLastError() != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    rc = KP_EHIP;
+  for (int r = 0; r <= reps && rc == KP_OK; ++r) {  // the first launch warms up
+    if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = KP_EHIP; break; }
+    hipLaunchKernelGGL(kp::k_read_probe, dim3(nblk), dim3(kp::kThreads), 0, ctx->stream,
+                       (const double2*)x, n2, sink);
+    float t = 0.f;
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, ctx->stream) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      rc = KP_EHIP;
+      break;
+    }
+    if (r) ms.push_back(t);
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(sink);
+  hipFree(x);
+  if (rc) {
+    snprintf(ctx->err, sizeof(ctx->err), "kp_read_bandwidth: HIP error");
+    return rc;
+  }
+  std::sort(ms.begin(), ms.end());
+  *gbps_host = (double)n2 * 16.0 / (1e-3 * ms[ms.size() / 2]) * 1e-9;
+  return KP_OK;
+}
+
+int kp_set_timeline(kp_ctx* ctx, long long* ts, int32_t kmax) {
+  if (!ctx || kmax < 0 || (kmax > 0 && !ts)) return KP_EINVAL;
+#ifdef KP_TIMELINE
+  ctx->ts = kmax > 0 ? ts : nullptr;
+  ctx->ts_kmax = kmax;
+  return KP_OK;
+#else
+  return KP_EUNSUPPORTED;
+#endif
+}
+
+int kp_timeline_layout(int32_t* slots_host, int32_t* workgroups_host) {
+  if (!slots_host || !workgroups_host) return KP_EINVAL;
+  *slots_host = kp::kTsSlots;
+  *workgroups_host = kp::kTsWgs;
+#ifdef KP_TIMELINE
+  return 1;
+#else
+  return 0;
+#endif
+}
 
 int kp_runtime_version(int32_t* runtime_host, int32_t* driver_host) {
   int rv = 0, dv = 0;

@@ -210,3 +210,38 @@ def test_integrate_rejects_bad_arguments():
     finally:
         lib.kp_destroy(h)
 
+
+
+def test_default_build_records_no_timeline():
+    """The timeline entry points exist in the default build: the layout is
+    reported, recording is refused as unsupported, bad arguments are
+    invalid (no GPU work)."""
+    lib = _lib.load()
+    slots, wgs = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.kp_timeline_layout(ctypes.byref(slots), ctypes.byref(wgs)) == 0
+    assert (slots.value, wgs.value) == (8, 256)
+    assert lib.kp_timeline_layout(None, ctypes.byref(wgs)) == _lib.KP_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.kp_create(ctypes.byref(h), None) == 0
+    try:
+        assert lib.kp_set_timeline(h, FAKE, 16) == _lib.KP_EUNSUPPORTED
+        assert lib.kp_set_timeline(h, None, 16) == _lib.KP_EINVAL
+        assert lib.kp_set_timeline(h, FAKE, -1) == _lib.KP_EINVAL
+    finally:
+        lib.kp_destroy(h)
+    assert lib.kp_set_timeline(None, FAKE, 16) == _lib.KP_EINVAL
+
+
+def test_read_bandwidth_rejects_bad_arguments():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.kp_create(ctypes.byref(h), None) == 0
+    out = ctypes.c_double()
+    try:
+        assert lib.kp_read_bandwidth(h, 1 << 30, 10, None) == _lib.KP_EINVAL
+        assert lib.kp_read_bandwidth(h, 1 << 19, 10, ctypes.byref(out)) == _lib.KP_EINVAL
+        assert lib.kp_read_bandwidth(h, 1 << 37, 10, ctypes.byref(out)) == _lib.KP_EINVAL
+        assert lib.kp_read_bandwidth(h, 1 << 30, 0, ctypes.byref(out)) == _lib.KP_EINVAL
+    finally:
+        lib.kp_destroy(h)
+    assert lib.kp_read_bandwidth(None, 1 << 30, 10, ctypes.byref(out)) == _lib.KP_EINVAL

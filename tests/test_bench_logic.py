@@ -87,3 +87,35 @@ def test_error_metrics():
     ref = np.array([1.0, -2.0, 2.0])
     e = bench.errors(ref + np.array([0.0, 0.03, 0.0]), ref)
     assert abs(e["rel_l2"] - 0.01) < 1e-15 and abs(e["max_abs_rel"] - 0.015) < 1e-15
+
+
+def test_timeline_summary_of_a_synthetic_call():
+    """Three phases on three workgroups (stamps in 100 MHz ticks): the start
+    phase, then Arnoldi steps j = 1 and 2; every interval checked by hand."""
+    import numpy as np
+    T = np.zeros((3, 3, 8))
+    T[0, 0, [0, 7]] = [100, 200]                  # start phase: released at 200
+    T[0, 0, 4] = 0
+    for k, (t0, j) in enumerate([(200, 1), (2200, 2)], start=1):
+        T[k, 0, 4] = 1000 + j                     # leader: phase code
+        T[k, 0, 0] = t0 + 10
+        for w, d in ((1, 0), (2, 40)):            # two other workgroups
+            T[k, w, 0] = t0 + 100 + d             # release seen
+            T[k, w, 1] = t0 + 500 + d             # update done
+            T[k, w, 2] = t0 + 600 + d             # flags seen
+            T[k, w, 3] = t0 + 1500 + d            # arrival
+        T[k, 0, 3] = t0 + 1400
+        T[k, 0, 5] = t0 + 1740                    # reduction 200 ticks after the last arrival
+        T[k, 0, 6] = t0 + 1900
+        T[k, 0, 7] = t0 + 2000                    # release: the next step starts from it
+    s = bench.timeline_summary(T)
+    assert s["arnoldi_steps"] == 2
+    m = s["step_mean_us"]
+    assert m["step_us"] == 20.0                   # 2000 ticks = 20 us each
+    assert m["release_seen_us"] == 1.2            # median of 100 and 140 ticks
+    assert m["update_done_us"] == 5.2 and m["halo_flags_us"] == 6.2
+    assert m["arrival_median_us"] == 15.2 and m["arrival_last_us"] == 15.4
+    assert m["reduction_after_last_us"] == 2.0
+    assert m["serial_us"] == 1.6 and m["release_us"] == 1.0
+    assert s["step_fit_us"]["intercept"] == 20.0 and s["step_fit_us"]["per_j"] == 0.0
+    assert s["other_phases"] == {}
