@@ -12,11 +12,12 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(session, config, items):
-    """Run the C-ABI client test (a child process that makes cooperative
-    launches) before any test of this process makes one: while a process that
-    has made a cooperative launch is alive, another process's cooperative
-    launch on the same GPU is refused by the runtime."""
-    first = [it for it in items if it.nodeid.split("::")[0].endswith("test_gpu_c_client.py")]
+    """Run the tests whose child processes make cooperative launches (the
+    C-ABI client, the timeline build) before any test of this process makes
+    one: while a process that has made a cooperative launch is alive, another
+    process's cooperative launch on the same GPU is refused by the runtime."""
+    children = ("test_gpu_c_client.py", "test_gpu_timeline.py")
+    first = [it for it in items if it.nodeid.split("::")[0].endswith(children)]
     if first:
         rest = [it for it in items if it not in first]
         items[:] = first + rest
