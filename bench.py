@@ -48,6 +48,7 @@ METRIC = "Arnoldi steps/s and phi_combo/s at N=1M,m=64; HBM GB/s vs peak; err vs
 KERNEL = "kp::k_run<double, false>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_run_allen_cahn_1024_traffic.txt")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_uneven_512_traffic.txt")
+FP32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_run_fp32_basis_brusselator_2048_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2410_14917_amd", "csrc")
 ORTHS = ("h-gsmgs", "h-cwy", "h-ncwy", "mgs", "iocgs")
 
@@ -639,6 +640,12 @@ def main():
                           "modelled_GBps": round(byts / (ms3 * 1e-3) / 1e9, 1),
                           "frac": round(byts / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "status": inf3["status"]}
+            if basis == "f32" and args.orth == "h-gsmgs":
+                # counters of the same call (committed summary, same kernel sources)
+                t3 = measured_traffic(FP32_TRAFFIC_FILE, "hbm_bytes_per_call")
+                leg[basis]["traffic"] = t3
+                leg[basis]["measured_GBps"] = (round(t3 / (ms3 * 1e-3) / 1e9, 1)
+                                               if t3 else None)
             # one fixed m = 64 substep: the error against the float64 oracle
             cf = kp.Context(orth=args.orth, basis=basis, fixed_m=64, fixed_substeps=1,
                             stream=stream)

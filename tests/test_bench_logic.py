@@ -38,7 +38,8 @@ def test_committed_summaries_parse():
     on and the byte counts bench.py reads (reported only while the hash
     matches the current sources)."""
     for path, key in ((bench.TRAFFIC_FILE, "hbm_bytes_per_launch"),
-                      (bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call")):
+                      (bench.BATCH_TRAFFIC_FILE, "hbm_bytes_per_call"),
+                      (bench.FP32_TRAFFIC_FILE, "hbm_bytes_per_call")):
         kv = {}
         for line in open(path):
             if "=" in line and not line.lstrip().startswith("#"):
