@@ -639,7 +639,8 @@ def main():
                           "arnoldi_steps_per_s": round(inf3["arnoldi_steps"] / (ms3 * 1e-3), 1),
                           "modelled_GBps": round(byts / (ms3 * 1e-3) / 1e9, 1),
                           "frac": round(byts / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          "status": inf3["status"]}
+                          "status": inf3["status"],
+                          "schedule": [[round(t, 8), m] for t, m in sch3]}
             if basis == "f32" and args.orth == "h-gsmgs":
                 # counters of the same call (committed summary, same kernel sources)
                 t3 = measured_traffic(FP32_TRAFFIC_FILE, "hbm_bytes_per_call")
