@@ -159,6 +159,8 @@ struct Args {
   int stop_j;         // pause when this many steps are completed (INT_MAX: never)
   int basis_f32;
   int halo_lds;       // the stencil halo rows fit the LDS copy of the matvec
+  int keep_xw;        // one plane, one sub-tile per workgroup, one-reduction form: the
+                      // matvec pass leaves x_j and w in LDS for the next update
 #ifdef KP_TIMELINE
   long long* ts;      // device timeline (see KP_TS), null when not recording
   int ts_kmax;        // phases the timeline holds

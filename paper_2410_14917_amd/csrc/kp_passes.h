@@ -214,9 +214,9 @@ __device__ inline void axpy_cols(const TB* V, int64_t ld, int64_t t0, int i0, in
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      acc[r].x += ci[c] * (double)v[c][r].x;
-      acc[r].y += ci[c] * (double)v[c][r].y;
+    for (int r = 0; r < kR; ++r) {   // fused multiply-adds, written out (update_pass
+      acc[r].x = __builtin_fma(ci[c], (double)v[c][r].x, acc[r].x);   // repeats them)
+      acc[r].y = __builtin_fma(ci[c], (double)v[c][r].y, acc[r].y);
     }
 }
 
@@ -602,7 +602,11 @@ __device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, i
   }
 }
 
-template <typename TB, bool HL>
+// KEEP (keep_xw: one plane, one sub-tile per workgroup): after the final
+// barrier, when no stencil reads the halo copy any more, each thread leaves
+// its pairs of x_j and w in the halo region of LDS (slot r * kThreads + tid
+// and (kR + r) * kThreads + tid, as double2) for the next phase's update.
+template <typename TB, bool HL, bool KEEP>
 __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Args& a, int jj, double* sacc, double* hl,
                                                         double* prow, double* own) {
   TB* V = reinterpret_cast<TB*>(a.V);
@@ -617,6 +621,7 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   TB* wcol = V + (int64_t)(jj + 1) * ld;
   const Src<TB> x{xcol, a.u, jj == 0};
   double sxx = 0.0, sxw = 0.0, sww = 0.0;
+  double2 kx[KEEP ? kR : 1], kw[KEEP ? kR : 1];
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
@@ -668,6 +673,13 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
         if (i2 < jj) load_chunk<TB, CC>(V, ld, t0, i2, min(CC, jj - i2), lo, va);
         dots_chunk<CC>(vb, xv, wv2, i1, min(CC, jj - i1), sacc);
       }
+      if constexpr (KEEP) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          kx[r] = xv[r];
+          kw[r] = wv2[r];
+        }
+      }
     }
   }
   sxx = wave_sum(sxx);
@@ -692,6 +704,14 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
     else
       cstore(prow + k, s);
   }
+  if constexpr (KEEP) {
+    double2* kp = reinterpret_cast<double2*>(hl);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      kp[r * kThreads + kp_tid()] = kx[r];
+      kp[(kR + r) * kThreads + kp_tid()] = kw[r];
+    }
+  }
 }
 
 // ---- basis update (Algorithm 4: projection and normalisation) --------------
@@ -702,8 +722,11 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
 // only when the Arnoldi process closes).  Columns are visited from the newest
 // to the oldest, so the ones the previous matvec pass read last come first.
 template <typename TB>
+// kxw: the pairs of x_jj and w the matvec pass of the previous phase left in
+// LDS (matvec_dots_pass with KEEP), or null: they are then read from the
+// basis.  Either way the columns enter in the same order (w, x_jj, ..., x_0).
 __device__ __attribute__((always_inline)) inline void update_pass(const Args& a, int jj, const double* coef, double* red,
-                                   bool want_norm) {
+                                   bool want_norm, const double* kxw) {
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
@@ -720,12 +743,25 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
       bool ok[kR];
       tile_pairs(q0, pend, lo, ok);
       double2 acc[kR];
+      int i1 = jj;
+      if (kxw) {
+        const double2* kp = reinterpret_cast<const double2*>(kxw);
+        const double cx = cload(coef + jj);
 #pragma unroll
-      for (int r = 0; r < kR; ++r) {
-        const double2 w = Pair<TB>::load(wcol + t0 + lo[r]);
-        acc[r] = make_double2(cw * w.x, cw * w.y);
+        for (int r = 0; r < kR; ++r) {
+          const double2 w = kp[(kR + r) * kThreads + kp_tid()];
+          const double2 x = kp[r * kThreads + kp_tid()];
+          acc[r] = make_double2(__builtin_fma(cx, x.x, cw * w.x), __builtin_fma(cx, x.y, cw * w.y));
+        }
+        i1 = jj - 1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const double2 w = Pair<TB>::load(wcol + t0 + lo[r]);
+          acc[r] = make_double2(cw * w.x, cw * w.y);
+        }
       }
-      for (int i1 = jj; i1 >= 0; i1 -= kCu)
+      for (; i1 >= 0; i1 -= kCu)
         axpy_cols<TB, kCu>(V, ld, t0, i1, -1, min(kCu, i1 + 1), coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {

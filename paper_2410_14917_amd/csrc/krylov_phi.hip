@@ -59,7 +59,7 @@ static_assert(kLdsDoubles >= 2 * kNmPad * kNmPad, "the small exponential does no
 // return cur holds the control of the next phase.
 template <typename TB, bool MS>
 __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, LeadLds& L, Ctl& cur, Ctl& nxt, int& ok,
-                          unsigned k) {
+                          int& kept, unsigned k) {
   double* sacc = lds + kOffSacc;
   double* grp = lds + kOffGrp;
   double* wk = lds + kOffWk;
@@ -89,7 +89,7 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       // (flag_publish also completes the reset above before the partial
       // sums are stored; without an update the wait is explicit)
       if (c.upd) {
-        update_pass<TB>(a, c.j - 1, a.pub->coef, red, false);
+        update_pass<TB>(a, c.j - 1, a.pub->coef, red, false, (a.keep_xw && kept == c.j - 1) ? hl : nullptr);
         flag_publish(a, k);
         flag_wait_neighbours(a, k);
       } else {
@@ -98,14 +98,19 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       {
         double* prow = step_part(a, k) + (int64_t)wg_rank(a) * kKStride;
         double* mine = lead ? own : nullptr;
-        if (a.halo_lds)
-          matvec_dots_pass<TB, true>(a, c.j, sacc, hl, prow, mine);
+        if (a.keep_xw)   // (implies halo_lds)
+          matvec_dots_pass<TB, true, true>(a, c.j, sacc, hl, prow, mine);
+        else if (a.halo_lds)
+          matvec_dots_pass<TB, true, false>(a, c.j, sacc, hl, prow, mine);
         else
-          matvec_dots_pass<TB, false>(a, c.j, sacc, hl, prow, mine);
+          matvec_dots_pass<TB, false, false>(a, c.j, sacc, hl, prow, mine);
+        // x_j and w stay in LDS (keep_xw) for the update of the next phase,
+        // which the leader always makes an update of column j + 1
+        if (a.keep_xw && kp_tid() == 0) kept = c.j;
       }
       break;
     case PH_CLOSE:
-      update_pass<TB>(a, c.j - 1, a.pub->coef, red, true);
+      update_pass<TB>(a, c.j - 1, a.pub->coef, red, true, (a.keep_xw && kept == c.j - 1) ? hl : nullptr);
       break;
     case PH_MVEC:
       if constexpr (MS) {
@@ -203,12 +208,14 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
 // The whole call (or, for the step-by-step entry, the steps up to stop_j).
 template <typename TB, bool MS>
 __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
-  __shared__ double lds[kLdsDoubles];
+  __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
   __shared__ LeadLds lead;
   __shared__ Ctl cur, nxt;
   __shared__ int ok;
+  __shared__ int kept;
   __shared__ unsigned s_k;
   if (kp_tid() == 0) {
+    kept = -1;
     // barriers released by earlier launches, and the control they announced
     const unsigned long long w = cload(release_word(a));
     s_k = (unsigned)(w >> 32);
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_run(Args a, int arnoldi_only) {
          ((cur.phase == PH_STEP || cur.phase == PH_MVEC) && cur.j >= a.stop_j)))
       break;
     ++k;
-    run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, k);
+    run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, kept, k);
   }
 }
 
@@ -351,13 +358,15 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchDesc d) {
 
 template <typename TB, bool MS>
 __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
-  __shared__ double lds[kLdsDoubles];
+  __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
   __shared__ LeadLds lead;
   __shared__ Ctl cur, nxt;
   __shared__ int ok, s_pi;
+  __shared__ int kept;   // keep_xw is off in batched calls; never set
   __shared__ unsigned s_k;
   const int t = __builtin_amdgcn_readfirstlane(d.team_of_wg[blockIdx.x]);
   if (t < 0) return;
+  if (kp_tid() == 0) kept = -1;
   const int c = __builtin_amdgcn_readfirstlane(d.team_class[t]);
   const bool lead_wg = (int)blockIdx.x == __builtin_amdgcn_readfirstlane(d.team_wg0[t]);
   unsigned long long* slot = d.slot + 8 * (size_t)t;
@@ -404,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchDesc d) {
       __syncthreads();
       if (!ok || cur.phase == PH_DONE) break;
       ++k;
-      run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, k);
+      run_phase<TB, MS>(a, lds, lead, cur, nxt, ok, kept, k);
     }
     __syncthreads();
     if (!ok) break;   // a bounded wait gave up: this team stops
@@ -649,7 +658,7 @@ __global__ __launch_bounds__(kThreads) void k_read_probe(const double2* x, int64
 
 // Small exponential alone (test entry): F = exp(tau Hbar_m) e_1 from st->H.
 __global__ __launch_bounds__(kThreads) void k_expm_test(Args a, int m, double tau) {
-  __shared__ double lds[kLdsDoubles];
+  __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
   expm_hbar(a, a.st->H, kLdh, m, tau, false, a.st->F, lds);
 }
 
@@ -902,6 +911,12 @@ void geometry(int ncu_slots, int rows_cfg, Args* a) {
   a->nwg = (int)((a->ny + rows - 1) / rows);
   a->nteam = a->nwg;
   a->part_rows = a->nwg;
+  // one plane whose rows per workgroup fit one sub-tile (kThreads * kR
+  // pairs), a one-reduction form: the matvec pass leaves x_j and w in the
+  // halo region of LDS (2 * kR * kThreads pairs) for the next update
+  a->keep_xw = (a->nplanes == 1 && rows * a->nx <= 2 * (int64_t)kp::kThreads * kp::kR &&
+                !kp::orth_multi_sync(a->orth) && 4 * kp::kR * kp::kThreads <= kp::kHaloCap)
+                   ? 1 : 0;
 }
 
 // Allocate the workspace for a problem and finish Args.
