@@ -137,6 +137,13 @@ def basis_bytes_per_call(schedule, p, c, n, s):
     return (total + 8) * n
 
 
+def onchip_bytes(info, n, s=8):
+    """Bytes of the two-pass count that the call kept on chip: the library
+    reports the vector passes (N elements of s bytes each) that stayed in LDS
+    (the update's x_j and w, the next matvec pass's x_{j+1}, the unstored w)."""
+    return info.get("onchip_passes", 0) * s * n
+
+
 def errors(y, ref):
     """Relative 2-norm error and max-abs error over max |ref|."""
     import numpy as np
@@ -445,6 +452,7 @@ def main():
     vec = vectors_per_call(sched, p, c_fields, args.orth)
     bytes_per_call = vec * 8.0 * N
     achieved = bytes_per_call / (avg_ms * 1e-3) / 1e9
+    kept = onchip_bytes(info, N, 8 if args.basis == "f64" else 4)
     # what a plain streaming read reaches on this device (1 GiB, same launch shape)
     read_ceiling = ctx.read_bandwidth(1 << 30, 20)
     log(f"plain streaming read: {read_ceiling:.1f} GB/s")
@@ -483,7 +491,13 @@ def main():
                      "kernel": KERNEL,
                      "bytes_per_launch": bytes_per_call, "avg_launch_ms": round(avg_ms, 4),
                      "read_ceiling_GBps": round(read_ceiling, 1),
-                     "frac_of_read_ceiling": round(achieved / read_ceiling, 4)},
+                     "frac_of_read_ceiling": round(achieved / read_ceiling, 4),
+                     # of bytes_per_launch, what the kernel keeps in LDS
+                     # between the matvec pass and the update, and the
+                     # fraction of peak counting only the bytes that move
+                     "bytes_kept_on_chip": kept,
+                     "frac_moved": round((bytes_per_call - kept) / (avg_ms * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 4)},
         "runtime": kp.runtime_info(),
     }
 

@@ -164,7 +164,14 @@ typedef struct kp_info {
     int32_t n_fallback;      /* steps where the exact norm replaced the estimate */
     int32_t breakdowns;      /* lucky breakdowns */
     int32_t schedule_len;    /* entries available through kp_get_schedule */
-    int32_t reserved;
+    int32_t onchip_passes;   /* vector passes (N elements each) of the two-pass
+                                count of Algorithm 4 that stayed in LDS: where
+                                each workgroup's rows fit one sub-tile (one
+                                plane, at most 4096 elements and rows of at
+                                most 2048, a one-reduction form) the update
+                                takes x_j and w from the matvec pass before
+                                it, that pass reads the updated x_{j+1} from
+                                LDS, and w is never stored; 0 otherwise */
     double  err_max;         /* largest substep error estimate */
     double  mu;              /* power-of-two balance of the augmented block */
     double  t_end;           /* time reached (h on success) */

@@ -72,12 +72,12 @@ class KpInfo(ctypes.Structure):
                 ("rejected", ctypes.c_int32), ("arnoldi_steps", ctypes.c_int32),
                 ("expm_evals", ctypes.c_int32), ("m_last", ctypes.c_int32),
                 ("n_fallback", ctypes.c_int32), ("breakdowns", ctypes.c_int32),
-                ("schedule_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("schedule_len", ctypes.c_int32), ("onchip_passes", ctypes.c_int32),
                 ("err_max", ctypes.c_double), ("mu", ctypes.c_double),
                 ("t_end", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None

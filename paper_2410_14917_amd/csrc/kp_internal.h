@@ -102,7 +102,8 @@ struct State {
   int nlog;
   int zero;           // the start vector is zero
   int m_last;
-  int pad_[3];
+  int onchip;         // vector passes of the two-pass count kept in LDS (keep_xw)
+  int pad_[2];
   double t, tau, beta, mu, err_max, omega, err, last_nrm2;
   double omega_prev;  // normalised error of the last accepted substep (PI control)
   double sigma[kMMax + 2];   // unit scale of stored basis column i

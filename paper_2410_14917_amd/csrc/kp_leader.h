@@ -195,7 +195,7 @@ struct LeadLds {
   double sigma[kMMax + 8];
   double gamma[kMMax + 8];
   double wn2[kMMax + 8];
-  int fallback_cur, m_target, breakdown, n_fallback, arnoldi_steps, pad_;
+  int fallback_cur, m_target, breakdown, n_fallback, arnoldi_steps, onchip;
 };
 
 __device__ inline void load_tables(const Args& a, LeadLds& L) {
@@ -216,6 +216,7 @@ __device__ inline void load_tables(const Args& a, LeadLds& L) {
     L.breakdown = st->breakdown;
     L.n_fallback = st->n_fallback;
     L.arnoldi_steps = st->arnoldi_steps;
+    L.onchip = st->onchip;
   }
   __syncthreads();
 }

@@ -80,6 +80,7 @@ __device__ inline double2 load_at(const TB* base, uint32_t byte_off) {
 // the stored basis column afterwards.  Own elements only (plain loads).
 template <typename TB>
 struct Src {
+  static constexpr bool kLds = false;
   const TB* col;
   const double* u;
   bool from_u;
@@ -93,6 +94,15 @@ struct Src {
     }
     return Pair<TB>::load(col + e);
   }
+};
+
+// x_j of a workgroup that owns one sub-tile, in LDS as the basis update left
+// it: element e of the block at l[e - t0] (t0: the block's first pair).
+struct LdsX {
+  static constexpr bool kLds = true;
+  const double* l;
+  int64_t t0;
+  __device__ double operator()(int64_t e) const { return l[e - t0]; }
 };
 
 // ---- ownership --------------------------------------------------------------
@@ -265,11 +275,11 @@ __device__ inline void stage_halo(const Args& a, const Rows& o, double* hl) {
 // ---- the operator on one grid element ---------------------------------------
 //
 // (A x)_e for grid element e (internal index) of plane s, whose in-plane index
-// is q (row, ix).  Neighbours inside the owned rows are read from x; the rows
-// just outside come from the LDS halo copy (HL) or from the coherent halo
+// is q (row, ix).  Neighbours inside the owned rows are read from x (the
+// basis column, or LDS where the update left x_j); the rows just outside come from the LDS halo copy (HL) or from the coherent halo
 // slots.  All loads are unconditional (dummy indices where unused).
-template <typename TB, bool HL>
-__device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x, const double* hl,
+template <typename TB, bool HL, typename XS>
+__device__ inline double op_elem(const Args& a, const Rows& o, const XS& x, const double* hl,
                                  int s, int64_t e, int q, bool valid) {
   const int nx = a.nx;
   int row = (int)((double)q * a.inv_nx);   // q / nx, corrected by one step
@@ -306,10 +316,13 @@ __device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x,
       xs = rnd<TB>(cload(a.hx + halo_at(a, (int)((unsigned)rs / (unsigned)a.rows_per_wg), s, 1, ix)));
     }
   }
+  // (the multiply-adds are written out, so that every instantiation of the
+  // stencil, x from the basis or from LDS, rounds alike)
   const double cxx = (s && !a.tangent) ? a.cx2 : a.cx, cyy = (s && !a.tangent) ? a.cy2 : a.cy;
-  const double lap = cxx * (xe + xw - 2.0 * c) + cyy * (xn + xs - 2.0 * c);
+  const double lap = __builtin_fma(cxx, __builtin_fma(-2.0, c, xe + xw),
+                                   cyy * __builtin_fma(-2.0, c, xn + xs));
   double tv = 0.0;
-  if (a.tangent && s == 0) {
+  if (!XS::kLds && a.tangent && s == 0) {   // (one plane when x is in LDS)
     // dA applied to the c half (plane 1) at the same point (Van Loan block)
     const int64_t o = a.npt_pad;
     const double c1 = xo;
@@ -330,28 +343,32 @@ __device__ inline double op_elem(const Args& a, const Rows& o, const Src<TB>& x,
         s1 = rnd<TB>(cload(a.hx + halo_at(a, (int)((unsigned)rs / (unsigned)a.rows_per_wg), 1, 1, ix)));
       }
     }
-    const double dadv = a.dadx * (e1 - w1) + a.dady * (n1 - s1);
-    tv = a.dcx * (e1 + w1 - 2.0 * c1) + a.dcy * (n1 + s1 - 2.0 * c1) +
-         (a.transpose ? dadv : -dadv) + a.dreact * c1;
+    const double dadv = __builtin_fma(a.dadx, e1 - w1, a.dady * (n1 - s1));
+    const double dlap = __builtin_fma(a.dcx, __builtin_fma(-2.0, c1, e1 + w1),
+                                      a.dcy * __builtin_fma(-2.0, c1, n1 + s1));
+    tv = __builtin_fma(a.dreact, c1, dlap + (a.transpose ? dadv : -dadv));
   }
   if (a.kind == KP_OP_ADR) {
-    const double adv = a.adx * (xe - xw) + a.ady * (xn - xs);
-    return lap + (a.transpose ? adv : -adv) + (a.react + U) * c + tv;
+    const double adv = __builtin_fma(a.adx, xe - xw, a.ady * (xn - xs));
+    return __builtin_fma(a.react + U, c, lap + (a.transpose ? adv : -adv)) + tv;
   }
-  if (a.kind == KP_OP_ALLEN_CAHN) return lap + (1.0 - 3.0 * U * U) * c + tv;
+  if (a.kind == KP_OP_ALLEN_CAHN) return __builtin_fma(__builtin_fma(-3.0 * U, U, 1.0), c, lap) + tv;
   // Brusselator Jacobian: pointwise blocks [[a11, a12], [a21, a22]]; the other
   // species at the same point (xo) is owned by this workgroup too.
-  const double a11 = 2.0 * U * W - (a.bb + 1.0), a12 = U * U;
-  const double a21 = a.bb - 2.0 * U * W, a22 = -U * U;
-  if (!a.transpose) return s ? lap + a21 * xo + a22 * c : lap + a11 * c + a12 * xo;
-  return s ? lap + a12 * xo + a22 * c : lap + a11 * c + a21 * xo;
+  const double a11 = __builtin_fma(2.0 * U, W, -(a.bb + 1.0)), a12 = U * U;
+  const double a21 = __builtin_fma(-2.0 * U, W, a.bb), a22 = -(U * U);
+  if (!a.transpose)
+    return s ? __builtin_fma(a22, c, __builtin_fma(a21, xo, lap))
+             : __builtin_fma(a12, xo, __builtin_fma(a11, c, lap));
+  return s ? __builtin_fma(a22, c, __builtin_fma(a12, xo, lap))
+           : __builtin_fma(a21, xo, __builtin_fma(a11, c, lap));
 }
 
 // (Atilde x) on the kR pairs of a sub-tile of plane segment sg:
 // A x_top + sum_c tc[c] b_{p-c} (the tail rows, K x_tail, are done by
 // tail_matvec_dots); zero in the padding.
-template <typename TB, bool HL>
-__device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, const Src<TB>& x,
+template <typename TB, bool HL, typename XS>
+__device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, const XS& x,
                                 const double* hl, int64_t t0, const uint32_t* lo,
                                 const double* tc, double2* w) {
   const int64_t base = (int64_t)sg.plane * a.npt_pad;
@@ -388,8 +405,8 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const bool v1 = t0 + lo[r] + 1 < sg.end;
-        w[r].x += t * b0[c][r][0];
-        w[r].y += v1 ? t * b0[c][r][1] : 0.0;
+        w[r].x = __builtin_fma(t, b0[c][r][0], w[r].x);
+        w[r].y = v1 ? __builtin_fma(t, b0[c][r][1], w[r].y) : w[r].y;
       }
     }
   }
@@ -414,8 +431,8 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
           const bool v1 = t0 + lo[r] + 1 < sg.end;
-          w[r].x += t * bv[c][r][0];
-          w[r].y += v1 ? t * bv[c][r][1] : 0.0;
+          w[r].x = __builtin_fma(t, bv[c][r][0], w[r].x);
+          w[r].y = v1 ? __builtin_fma(t, bv[c][r][1], w[r].y) : w[r].y;
         }
       }
     }
@@ -577,8 +594,8 @@ __device__ inline void dots_chunk(const R (&v)[C][kR], const double2* xv,
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
       const double vx = (double)v[c][r].x, vy = (double)v[c][r].y;
-      ax += vx * xv[r].x + vy * xv[r].y;
-      aw += vx * wv2[r].x + vy * wv2[r].y;
+      ax = __builtin_fma(vy, xv[r].y, __builtin_fma(vx, xv[r].x, ax));
+      aw = __builtin_fma(vy, wv2[r].y, __builtin_fma(vx, wv2[r].x, aw));
     }
     if (c < nc) {
       ax = wave_sum(ax);
@@ -602,26 +619,32 @@ __device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, i
   }
 }
 
-// KEEP (keep_xw: one plane, one sub-tile per workgroup): after the final
-// barrier, when no stencil reads the halo copy any more, each thread leaves
-// its pairs of x_j and w in the halo region of LDS (slot r * kThreads + tid
-// and (kR + r) * kThreads + tid, as double2) for the next phase's update.
-template <typename TB, bool HL, bool KEEP>
+// KEEP (keep_xw: one plane, one sub-tile per workgroup): the region hl of LDS
+// holds x_j as pairs (slot r * kThreads + tid, i.e. element e of the block at
+// hl[e - t0]) and w (slot (kR + r) * kThreads + tid), both as double2; the
+// halo copy moves to the w half.  After the final barrier, when no stencil
+// reads either any more, each thread leaves its pairs of x_j and w there for
+// the next phase's update, which then needs neither from the basis: w is not
+// stored.  XL (with KEEP): the update of this phase has left x_j in the x
+// half, so the stencil and the inner products read it from LDS.
+template <typename TB, bool HL, bool KEEP, bool XL>
 __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Args& a, int jj, double* sacc, double* hl,
                                                         double* prow, double* own) {
+  static_assert(KEEP || !XL, "x_j is in LDS only where the pass keeps x_j and w");
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
   const Rows o = own_rows(a);
+  double* hh = KEEP ? hl + 2 * kR * kThreads : hl;   // the halo copy
   for (int k = kp_tid(); k < kWaves * kKStride; k += kThreads) sacc[k] = 0.0;
-  if (HL) stage_halo<TB>(a, o, hl);
+  if (HL) stage_halo<TB>(a, o, hh);
   const double inv_mu = cload(&a.pub->inv_mu);
   __syncthreads();
   TB* xcol = V + (int64_t)jj * ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
   const Src<TB> x{xcol, a.u, jj == 0};
   double sxx = 0.0, sxw = 0.0, sww = 0.0;
-  double2 kx[KEEP ? kR : 1], kw[KEEP ? kR : 1];
+  double2 kx[KEEP && !XL ? kR : 1], kw[KEEP ? kR : 1];   // (with XL, x_j stays where it is)
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
@@ -641,15 +664,22 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       double2 xv[kR], wv2[kR];
       constexpr int CC = Raw<TB>::kCols;
       typename Raw<TB>::type va[CC][kR], vb[CC][kR];
+      if constexpr (XL) {
+        const LdsX lx{hl, t0};   // (one sub-tile: t0 is the block's first pair)
 #pragma unroll
-      for (int r = 0; r < kR; ++r) xv[r] = x.pair(t0 + lo[r]);
-      aug_tile<TB, HL>(a, o, sg, x, hl, t0, lo, tc, wv2);
+        for (int r = 0; r < kR; ++r) xv[r] = *reinterpret_cast<const double2*>(hl + lo[r]);
+        aug_tile<TB, HL>(a, o, sg, lx, hh, t0, lo, tc, wv2);
+      } else {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) xv[r] = x.pair(t0 + lo[r]);
+        aug_tile<TB, HL>(a, o, sg, x, hh, t0, lo, tc, wv2);
+      }
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         wv2[r].x = rnd<TB>(wv2[r].x);
         wv2[r].y = rnd<TB>(wv2[r].y);
         if (ok[r]) {
-          Pair<TB>::store(wcol + t0 + lo[r], wv2[r].x, wv2[r].y);
+          if (!KEEP) Pair<TB>::store(wcol + t0 + lo[r], wv2[r].x, wv2[r].y);
           if (jj == 0) Pair<TB>::store(xcol + t0 + lo[r], xv[r].x, xv[r].y);
         } else {
           xv[r] = make_double2(0.0, 0.0);
@@ -658,9 +688,9 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       }
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
-        sxx += xv[r].x * xv[r].x + xv[r].y * xv[r].y;
-        sxw += xv[r].x * wv2[r].x + xv[r].y * wv2[r].y;
-        sww += wv2[r].x * wv2[r].x + wv2[r].y * wv2[r].y;
+        sxx = __builtin_fma(xv[r].y, xv[r].y, __builtin_fma(xv[r].x, xv[r].x, sxx));
+        sxw = __builtin_fma(xv[r].y, wv2[r].y, __builtin_fma(xv[r].x, wv2[r].x, sxw));
+        sww = __builtin_fma(wv2[r].y, wv2[r].y, __builtin_fma(wv2[r].x, wv2[r].x, sww));
       }
       // x_i . x and x_i . w for the older columns, two chunks in flight
       if (jj > 0) load_chunk<TB, CC>(V, ld, t0, 0, min(CC, jj), lo, va);
@@ -676,7 +706,7 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       if constexpr (KEEP) {
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-          kx[r] = xv[r];
+          if constexpr (!XL) kx[r] = xv[r];
           kw[r] = wv2[r];
         }
       }
@@ -708,7 +738,7 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
     double2* kp = reinterpret_cast<double2*>(hl);
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-      kp[r * kThreads + kp_tid()] = kx[r];
+      if constexpr (!XL) kp[r * kThreads + kp_tid()] = kx[r];
       kp[(kR + r) * kThreads + kp_tid()] = kw[r];
     }
   }
@@ -725,8 +755,11 @@ template <typename TB>
 // kxw: the pairs of x_jj and w the matvec pass of the previous phase left in
 // LDS (matvec_dots_pass with KEEP), or null: they are then read from the
 // basis.  Either way the columns enter in the same order (w, x_jj, ..., x_0).
+// With kxw each thread also leaves its pairs of the new vector in the slots of
+// x_jj (its own slots, so no barrier is needed), where the next matvec pass
+// reads them.
 __device__ __attribute__((always_inline)) inline void update_pass(const Args& a, int jj, const double* coef, double* red,
-                                   bool want_norm, const double* kxw) {
+                                   bool want_norm, double* kxw) {
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
@@ -767,6 +800,7 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
       for (int r = 0; r < kR; ++r) {
         const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
         if (ok[r]) {
+          if (kxw) reinterpret_cast<double2*>(kxw)[r * kThreads + kp_tid()] = make_double2(y0, y1);
           Pair<TB>::store(wcol + t0 + lo[r], y0, y1);
           ss += y0 * y0 + y1 * y1;
           publish_pair(a, sg, t0 + lo[r], y0, y1);
@@ -917,9 +951,9 @@ __device__ __attribute__((always_inline)) inline void mvec_pass(const Args& a, i
           xv[r] = make_double2(0.0, 0.0);
           wv2[r] = make_double2(0.0, 0.0);
         }
-        sxx += xv[r].x * xv[r].x + xv[r].y * xv[r].y;
-        sxw += xv[r].x * wv2[r].x + xv[r].y * wv2[r].y;
-        sww += wv2[r].x * wv2[r].x + wv2[r].y * wv2[r].y;
+        sxx = __builtin_fma(xv[r].y, xv[r].y, __builtin_fma(xv[r].x, xv[r].x, sxx));
+        sxw = __builtin_fma(xv[r].y, wv2[r].y, __builtin_fma(xv[r].x, wv2[r].x, sxw));
+        sww = __builtin_fma(wv2[r].y, wv2[r].y, __builtin_fma(wv2[r].x, wv2[r].x, sww));
         saw += av[r].x * wv2[r].x + av[r].y * wv2[r].y;
       }
     }

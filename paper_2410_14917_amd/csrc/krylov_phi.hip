@@ -69,6 +69,8 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
   double* hl = lds + kOffHl;
   const bool lead = wg_rank(a) == 0;
   const Ctl c = cur;
+  // the matvec pass of the previous phase left x_{j-1} and w in LDS
+  const bool xl = a.keep_xw && kept == c.j - 1;
   KP_TS(a, k, 0);
   if (lead) KP_TSV(a, k, 4, c.phase * 1000 + c.j);
   // this workgroup's row of the step buffer of barrier k + 1 is free again
@@ -88,8 +90,12 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       // step), then the matvec + grouped dots of step j: one grid-wide sync
       // (flag_publish also completes the reset above before the partial
       // sums are stored; without an update the wait is explicit)
+      // (with keep_xw, x_{j-1} and w are in LDS from the matvec pass of the
+      // previous phase, and the update leaves x_j there for this one: every
+      // update directly follows the matvec pass of the same Arnoldi process
+      // in the same launch, since a launch pauses only after a close)
       if (c.upd) {
-        update_pass<TB>(a, c.j - 1, a.pub->coef, red, false, (a.keep_xw && kept == c.j - 1) ? hl : nullptr);
+        update_pass<TB>(a, c.j - 1, a.pub->coef, red, false, xl ? hl : nullptr);
         flag_publish(a, k);
         flag_wait_neighbours(a, k);
       } else {
@@ -98,19 +104,21 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
       {
         double* prow = step_part(a, k) + (int64_t)wg_rank(a) * kKStride;
         double* mine = lead ? own : nullptr;
-        if (a.keep_xw)   // (implies halo_lds)
-          matvec_dots_pass<TB, true, true>(a, c.j, sacc, hl, prow, mine);
+        if (a.keep_xw && c.upd && xl)   // (keep_xw implies halo_lds)
+          matvec_dots_pass<TB, true, true, true>(a, c.j, sacc, hl, prow, mine);
+        else if (a.keep_xw)
+          matvec_dots_pass<TB, true, true, false>(a, c.j, sacc, hl, prow, mine);
         else if (a.halo_lds)
-          matvec_dots_pass<TB, true, false>(a, c.j, sacc, hl, prow, mine);
+          matvec_dots_pass<TB, true, false, false>(a, c.j, sacc, hl, prow, mine);
         else
-          matvec_dots_pass<TB, false, false>(a, c.j, sacc, hl, prow, mine);
+          matvec_dots_pass<TB, false, false, false>(a, c.j, sacc, hl, prow, mine);
         // x_j and w stay in LDS (keep_xw) for the update of the next phase,
         // which the leader always makes an update of column j + 1
         if (a.keep_xw && kp_tid() == 0) kept = c.j;
       }
       break;
     case PH_CLOSE:
-      update_pass<TB>(a, c.j - 1, a.pub->coef, red, true, (a.keep_xw && kept == c.j - 1) ? hl : nullptr);
+      update_pass<TB>(a, c.j - 1, a.pub->coef, red, true, xl ? hl : nullptr);
       break;
     case PH_MVEC:
       if constexpr (MS) {
@@ -160,6 +168,13 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
     if (!ok) return;
   }
   if (kp_tid() == 0) nxt = c;
+  if (a.keep_xw && kp_tid() == 0 && (c.phase == PH_STEP || c.phase == PH_CLOSE)) {
+    // vector passes of the two-pass count that stayed in LDS: the update's
+    // x_{j-1} and w, the matvec's x_j, and the w it did not store
+    const bool upd = (c.phase == PH_CLOSE || c.upd) && xl;
+    L.onchip += (upd ? 2 : 0) + (c.phase == PH_STEP ? (upd ? 2 : 1) : 0);
+    a.st->onchip = L.onchip;
+  }
   switch (c.phase) {
     case PH_STAGE:
       leader_stage(a, red, nxt);
@@ -272,6 +287,7 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   st->substeps = st->rejected = st->arnoldi_steps = st->expm_evals = 0;
   st->n_fallback = st->breakdowns = st->nlog = st->zero = 0;
   st->m_last = 0;
+  st->onchip = 0;
   st->t = 0.0;
   st->tau = a.tau0;
   st->beta = 0.0;
@@ -440,7 +456,7 @@ __global__ __launch_bounds__(64) void k_batch_info(BatchDesc d, kp_info* out) {
   r.n_fallback = st->n_fallback;
   r.breakdowns = st->breakdowns;
   r.schedule_len = min(st->nlog, kLogMax);
-  r.reserved = 0;
+  r.onchip_passes = st->onchip;   // (0: batched problems keep nothing in LDS)
   r.err_max = st->err_max;
   r.mu = st->mu;
   r.t_end = st->t;
@@ -913,8 +929,11 @@ void geometry(int ncu_slots, int rows_cfg, Args* a) {
   a->part_rows = a->nwg;
   // one plane whose rows per workgroup fit one sub-tile (kThreads * kR
   // pairs), a one-reduction form: the matvec pass leaves x_j and w in the
-  // halo region of LDS (2 * kR * kThreads pairs) for the next update
+  // halo region of LDS (2 * kR * kThreads pairs) for the next update, which
+  // leaves x_{j+1} there for the next matvec pass; that pass's halo copy (two
+  // rows) goes to the w half
   a->keep_xw = (a->nplanes == 1 && rows * a->nx <= 2 * (int64_t)kp::kThreads * kp::kR &&
+                2 * (int64_t)a->nx <= 2 * (int64_t)kp::kThreads * kp::kR &&
                 !kp::orth_multi_sync(a->orth) && 4 * kp::kR * kp::kThreads <= kp::kHaloCap)
                    ? 1 : 0;
 }
@@ -1049,6 +1068,7 @@ int fill_info_from(kp_ctx* ctx, const Args& a, kp_info* info) {
   info->err_max = h.err_max;
   info->mu = h.mu;
   info->t_end = h.t;
+  info->onchip_passes = h.onchip;
   return KP_OK;
 }
 

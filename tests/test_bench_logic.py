@@ -120,3 +120,10 @@ def test_timeline_summary_of_a_synthetic_call():
     assert m["serial_us"] == 1.6 and m["release_us"] == 1.0
     assert s["step_fit_us"]["intercept"] == 20.0 and s["step_fit_us"]["per_j"] == 0.0
     assert s["other_phases"] == {}
+
+
+def test_onchip_bytes_by_hand():
+    # 3584 passes kept on chip, N = 1M float64; FP32 basis elements; none
+    assert bench.onchip_bytes({"onchip_passes": 3584}, 1 << 20) == 3584 * 8 * (1 << 20)
+    assert bench.onchip_bytes({"onchip_passes": 10}, 100, 4) == 10 * 4 * 100
+    assert bench.onchip_bytes({"onchip_passes": 0}, 1 << 20) == 0
