@@ -915,10 +915,19 @@ int grow(kp_ctx* ctx, void** p, size_t* have, size_t need) {
 // At least one full sub-tile (kThreads * kR pairs) of elements per workgroup
 // (or the configured rows_per_wg), at most one workgroup per co-resident slot;
 // an even row count when nx is odd keeps every segment start even (pair
-// alignment).
+// alignment).  Where a one-reduction form runs on one plane, the largest row
+// count whose rows fit one sub-tile is taken instead when the co-resident
+// workgroups still cover the grid with it: x_j and w then stay on chip
+// between the passes (keep_xw below).
 void geometry(int ncu_slots, int rows_cfg, Args* a) {
   const int64_t per_wg_min = (int64_t)kp::kThreads * kp::kR * 2;
   int64_t rows = (per_wg_min + (int64_t)a->nx * a->nplanes - 1) / ((int64_t)a->nx * a->nplanes);
+  if (rows_cfg <= 0 && a->nplanes == 1 && 2 * (int64_t)a->nx <= per_wg_min &&
+      !kp::orth_multi_sync(a->orth)) {
+    int64_t rk = per_wg_min / a->nx;
+    if ((a->nx & 1) && (rk & 1) && rk < a->ny) --rk;
+    if (rk >= 1 && rk < rows && (a->ny + rk - 1) / rk <= ncu_slots) rows = rk;
+  }
   if (rows_cfg > 0) rows = rows_cfg;
   rows = std::max<int64_t>(rows, (a->ny + ncu_slots - 1) / ncu_slots);
   rows = std::max<int64_t>(1, std::min<int64_t>(rows, a->ny));
