@@ -317,11 +317,12 @@ def timeline_summary(T, rate=100e6):
     return out
 
 
-def run_timeline(outdir, side=1024):
+def run_timeline(outdir, side=1024, workload="allen-cahn"):
     """Record the device timeline of the benchmark call and of one fixed
-    m = 64 substep with the timeline build of the library; write the raw
-    stamps (.npy) and the summaries (.json) to outdir and print the
-    summaries without their per-step rows."""
+    m = 64 substep with the timeline build of the library (workload
+    "brusselator": the 2 x side^2 Brusselator call with the float32 and the
+    float64 basis instead); write the raw stamps (.npy) and the summaries
+    (.json) to outdir and print the summaries without their per-step rows."""
     import numpy as np
     from paper_2410_14917_amd import _lib
     lib = _lib.load(_lib.TIMELINE_LIB_PATH)        # before anything loads the default build
@@ -333,14 +334,19 @@ def run_timeline(outdir, side=1024):
     if lib.kp_timeline_layout(ctypes.byref(slots), ctypes.byref(wgs)) != 1:
         raise RuntimeError("the loaded library does not record timelines")
     os.makedirs(outdir, exist_ok=True)
-    pr = W.config2(side=side)
+    if workload == "brusselator":
+        pr = W.config3(side=side)
+        runs = (("f32_adaptive", dict(basis="f32")), ("f64_adaptive", {}))
+    else:
+        pr = W.config2(side=side)
+        runs = (("adaptive", {}), ("fixed_m64", dict(fixed_m=64, fixed_substeps=1)))
     op = kp.Operator.from_host(pr.op)
     B = torch.as_tensor(np.ascontiguousarray(pr.B.T), device="cuda")
     out = torch.empty(pr.op.n, dtype=torch.float64, device="cuda")
     kmax = 4096
     ts = torch.zeros(kmax * wgs.value * slots.value, dtype=torch.int64, device="cuda")
     result = {}
-    for label, kw in (("adaptive", {}), ("fixed_m64", dict(fixed_m=64, fixed_substeps=1))):
+    for label, kw in runs:
         with kp.Context(**kw) as ctx:
             ctx.phi_combo(op, B, pr.h, tol=pr.tol, m_max=64, out=out)
             ts.zero_()
@@ -389,6 +395,10 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--dump", metavar="DIR",
                     help="only write the workload arrays and kp_run arguments to DIR")
+    ap.add_argument("--timeline-workload", default="allen-cahn",
+                    choices=("allen-cahn", "brusselator"),
+                    help="with --timeline: the benchmark call, or the 2 x 2048^2 Brusselator "
+                         "call with the float32 and float64 bases (--side 2048)")
     ap.add_argument("--timeline", metavar="DIR",
                     help="only record the per-phase device timeline of the benchmark call "
                          "(timeline build of the library) into DIR")
@@ -397,7 +407,7 @@ def main():
         dump_inputs(args.dump)
         return
     if args.timeline:
-        run_timeline(args.timeline, side=args.side)
+        run_timeline(args.timeline, side=args.side, workload=args.timeline_workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
