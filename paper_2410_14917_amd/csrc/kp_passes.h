@@ -96,6 +96,18 @@ struct Src {
   }
 };
 
+// A plain basis column: the matvec passes read x_j through it, having copied
+// the state into column 0 before the first step's pass, so that no element
+// load chooses between two sources (such a choice put a branch, and a wait for
+// memory, after every load of the stencil).
+template <typename TB>
+struct Col {
+  static constexpr bool kLds = false;
+  const TB* col;
+  __device__ double operator()(int64_t e) const { return (double)col[e]; }
+  __device__ double2 pair(int64_t e) const { return Pair<TB>::load(col + e); }
+};
+
 // x_j of a workgroup that owns one sub-tile, in LDS as the basis update left
 // it: element e of the block at l[e - t0] (t0: the block's first pair).
 struct LdsX {
@@ -148,6 +160,19 @@ __device__ inline double* out_plane(const Args& a, int s) {
 // tangent mode): entry k takes entry k+1 unless k closes its block.
 __device__ inline bool tail_shift_in(const Args& a, int k) {
   return k + 1 < a.p && ((k + 1) % a.pb) != 0;
+}
+
+// Copies the state u (rounded to the basis type) into column 0 over the
+// workgroup's own pairs (with the padding element of an odd segment end),
+// before the first step's matvec pass reads it there (the pass's barrier
+// orders the stores before the loads).
+template <typename TB>
+__device__ inline void copy_state(const Args& a, const Rows& o, TB* col0) {
+  for (int si = 0; si < num_segs(a); ++si) {
+    const Seg sg = seg_at(a, o, si);
+    const int64_t end = 2 * ((sg.end + 1) >> 1);
+    for (int64_t e = sg.beg + kp_tid(); e < end; e += kThreads) col0[e] = (TB)a.u[e];
+  }
 }
 
 constexpr int kR = 4;    // element pairs per thread per sub-tile
@@ -639,10 +664,12 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   for (int k = kp_tid(); k < kWaves * kKStride; k += kThreads) sacc[k] = 0.0;
   if (HL) stage_halo<TB>(a, o, hh);
   const double inv_mu = cload(&a.pub->inv_mu);
-  __syncthreads();
   TB* xcol = V + (int64_t)jj * ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
-  const Src<TB> x{xcol, a.u, jj == 0};
+  const Src<TB> x{xcol, a.u, jj == 0};   // (the tail entries)
+  const Col<TB> xc{xcol};
+  if (jj == 0) copy_state<TB>(a, o, xcol);
+  __syncthreads();
   double sxx = 0.0, sxw = 0.0, sww = 0.0;
   double2 kx[KEEP && !XL ? kR : 1], kw[KEEP ? kR : 1];   // (with XL, x_j stays where it is)
   const int ns = num_segs(a);
@@ -664,6 +691,8 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       double2 xv[kR], wv2[kR];
       constexpr int CC = Raw<TB>::kCols;
       typename Raw<TB>::type va[CC][kR], vb[CC][kR];
+      // (the first chunk of older columns goes out with the stencil's loads)
+      if (jj > 0) load_chunk<TB, CC>(V, ld, t0, 0, min(CC, jj), lo, va);
       if constexpr (XL) {
         const LdsX lx{hl, t0};   // (one sub-tile: t0 is the block's first pair)
 #pragma unroll
@@ -671,8 +700,8 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
         aug_tile<TB, HL>(a, o, sg, lx, hh, t0, lo, tc, wv2);
       } else {
 #pragma unroll
-        for (int r = 0; r < kR; ++r) xv[r] = x.pair(t0 + lo[r]);
-        aug_tile<TB, HL>(a, o, sg, x, hh, t0, lo, tc, wv2);
+        for (int r = 0; r < kR; ++r) xv[r] = xc.pair(t0 + lo[r]);
+        aug_tile<TB, HL>(a, o, sg, xc, hh, t0, lo, tc, wv2);
       }
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
@@ -693,7 +722,6 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
         sww = __builtin_fma(wv2[r].y, wv2[r].y, __builtin_fma(wv2[r].x, wv2[r].x, sww));
       }
       // x_i . x and x_i . w for the older columns, two chunks in flight
-      if (jj > 0) load_chunk<TB, CC>(V, ld, t0, 0, min(CC, jj), lo, va);
       for (int i0 = 0; i0 < jj; i0 += 2 * CC) {
         const int i1 = i0 + CC;
         if (i1 < jj) load_chunk<TB, CC>(V, ld, t0, i1, min(CC, jj - i1), lo, vb);
@@ -912,11 +940,13 @@ __device__ __attribute__((always_inline)) inline void mvec_pass(const Args& a, i
   if (HL) stage_halo<TB>(a, o, hl);
   const double inv_mu = cload(&a.pub->inv_mu);
   const double xs = jj == 0 ? 1.0 : cload(&a.pub->xscale);
-  __syncthreads();
   TB* xcol = V + (int64_t)jj * ld;
   TB* wcol = V + (int64_t)(jj + 1) * ld;
   const TB* acp = V + (int64_t)(acol >= 0 ? acol : 0) * ld;
-  const Src<TB> x{xcol, a.u, jj == 0};
+  const Src<TB> x{xcol, a.u, jj == 0};   // (the tail entries)
+  const Col<TB> xc{xcol};
+  if (jj == 0) copy_state<TB>(a, o, xcol);
+  __syncthreads();
   double sxx = 0.0, sxw = 0.0, sww = 0.0, saw = 0.0;
   const int ns = num_segs(a);
   for (int si = 0; si < ns; ++si) {
@@ -936,10 +966,10 @@ __device__ __attribute__((always_inline)) inline void mvec_pass(const Args& a, i
       const TB* ac = uniform_ptr(acp + t0);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
-        xv[r] = x.pair(t0 + lo[r]);
+        xv[r] = xc.pair(t0 + lo[r]);
         av[r] = (acol >= 0) ? load_at(ac, lo[r] * (uint32_t)sizeof(TB)) : make_double2(0.0, 0.0);
       }
-      aug_tile<TB, HL>(a, o, sg, x, hl, t0, lo, tc, wv2);
+      aug_tile<TB, HL>(a, o, sg, xc, hl, t0, lo, tc, wv2);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         wv2[r].x = rnd<TB>(xs * wv2[r].x);
