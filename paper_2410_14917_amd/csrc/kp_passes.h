@@ -464,6 +464,140 @@ __device__ inline void aug_tile(const Args& a, const Rows& o, const Seg& sg, con
   }
 }
 
+// ---- both species of the Brusselator at one grid point ------------------------
+//
+// The two planes of the Brusselator Jacobian couple only pointwise, so one
+// pass can take both species of a grid point together: the fields U, W and
+// both centres are loaded once for the two results (each species is the
+// other's coupling term), and one memory round trip yields two elements.
+// Element e is in plane 0 (in-plane index q), e + npt_pad its partner in
+// plane 1; y0, y1 round exactly as op_elem's results for the two planes.
+template <typename TB, bool HL, typename XS>
+__device__ inline void op_br2(const Args& a, const Rows& o, const XS& x, const double* hl,
+                              int64_t e, int q, bool valid, double& y0, double& y1) {
+  const int nx = a.nx;
+  const int64_t P = a.npt_pad;
+  int row = (int)((double)q * a.inv_nx);   // q / nx, corrected by one step
+  row -= ((unsigned)row * (unsigned)nx > (unsigned)q) ? 1 : 0;
+  row += ((unsigned)(row + 1) * (unsigned)nx <= (unsigned)q) ? 1 : 0;
+  const int ix = q - row * nx;
+  const bool hn = row + 1 < o.r1, hs = row > o.r0;
+  const int64_t ie = (valid && ix != nx - 1) ? e + 1 : (valid ? e - ix : e);
+  const int64_t iw = (valid && ix != 0) ? e - 1 : (valid ? e + nx - 1 : e);
+  const int64_t in = (hn && valid) ? e + nx : e;
+  const int64_t is = (hs && valid) ? e - nx : e;
+  const double c0 = x(e), c1 = x(e + P);
+  const double e0 = x(ie), e1 = x(ie + P);
+  const double w0 = x(iw), w1 = x(iw + P);
+  double n0 = x(in), n1 = x(in + P);
+  double s0 = x(is), s1 = x(is + P);
+  const int qf = valid ? q : 0;
+  const double U = a.f0[qf], W = a.f1[qf];
+  if (HL) {
+    n0 = hn ? n0 : hl[0 * nx + ix];
+    n1 = hn ? n1 : hl[1 * nx + ix];
+    s0 = hs ? s0 : hl[2 * nx + ix];
+    s1 = hs ? s1 : hl[3 * nx + ix];
+  } else {
+    if (!hn) {
+      const int rn = (row + 1 == a.ny) ? 0 : row + 1;
+      const int wn = (int)((unsigned)rn / (unsigned)a.rows_per_wg);
+      n0 = rnd<TB>(cload(a.hx + halo_at(a, wn, 0, 0, ix)));
+      n1 = rnd<TB>(cload(a.hx + halo_at(a, wn, 1, 0, ix)));
+    }
+    if (!hs) {
+      const int rs = (row == 0) ? a.ny - 1 : row - 1;
+      const int ws = (int)((unsigned)rs / (unsigned)a.rows_per_wg);
+      s0 = rnd<TB>(cload(a.hx + halo_at(a, ws, 0, 1, ix)));
+      s1 = rnd<TB>(cload(a.hx + halo_at(a, ws, 1, 1, ix)));
+    }
+  }
+  const double lap0 = __builtin_fma(a.cx, __builtin_fma(-2.0, c0, e0 + w0),
+                                    a.cy * __builtin_fma(-2.0, c0, n0 + s0));
+  const double lap1 = __builtin_fma(a.cx2, __builtin_fma(-2.0, c1, e1 + w1),
+                                    a.cy2 * __builtin_fma(-2.0, c1, n1 + s1));
+  const double a11 = __builtin_fma(2.0 * U, W, -(a.bb + 1.0)), a12 = U * U;
+  const double a21 = __builtin_fma(-2.0 * U, W, a.bb), a22 = -(U * U);
+  const double k0 = a.transpose ? a21 : a12, k1 = a.transpose ? a12 : a21;
+  y0 = __builtin_fma(k0, c1, __builtin_fma(a11, c0, lap0));
+  y1 = __builtin_fma(a22, c1, __builtin_fma(k1, c0, lap1));
+}
+
+// Pairs of a joint sub-tile: pairs r < kR/2 at in-plane pair positions
+// q0 + r * kThreads + tid of plane 0, pairs r >= kR/2 at the same positions in
+// plane 1 (offset npt_pad); clamped and flagged like tile_pairs.
+__device__ inline void tile_pairs_joint(int64_t q0, int64_t pend, int64_t P, uint32_t* lo,
+                                        bool* ok) {
+#pragma unroll
+  for (int r = 0; r < kR / 2; ++r) {
+    const int64_t q = q0 + (int64_t)r * kThreads + kp_tid();
+    ok[r] = ok[r + kR / 2] = q < pend;
+    lo[r] = (uint32_t)(2 * ((ok[r] ? q : pend - 1) - q0));
+    lo[r + kR / 2] = lo[r] + (uint32_t)P;
+  }
+}
+
+// (Atilde x) on a joint sub-tile (both species, plane-0 segment sg): the
+// stencil by op_br2, then sum_c tc[c] b_{p-c} on each plane's pairs.
+template <typename TB, bool HL, typename XS>
+__device__ inline void aug_tile_br2(const Args& a, const Rows& o, const Seg& sg, const XS& x,
+                                    const double* hl, int64_t t0, const uint32_t* lo,
+                                    const double* tc, double2* w) {
+  // plane s's pairs sit at s * npt in the caller's B, at s * npt_pad here
+  const int64_t boff1 = (int64_t)a.npt - a.npt_pad;
+  bool v1[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) v1[r] = t0 + lo[r % (kR / 2)] + 1 < sg.end;
+  // the columns b_{p-c}, two at a time; the first two go out with the
+  // stencil's loads
+  auto load_b = [&](int c0, double (&bv)[2][kR][2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c0 + c < a.pb) {
+        const int64_t col = (int64_t)(a.pb - c0 - c) * a.ldb;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const int64_t e = t0 + lo[r];
+          const int64_t ce = col + (r < kR / 2 ? 0 : boff1);
+          bv[c][r][0] = a.B[ce + e];
+          bv[c][r][1] = a.B[ce + (v1[r] ? e + 1 : e)];
+        }
+      }
+    }
+  };
+  auto add_b = [&](int c0, const double (&bv)[2][kR][2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c0 + c < a.pb) {
+        const double t = tc[c0 + c];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          w[r].x = __builtin_fma(t, bv[c][r][0], w[r].x);
+          w[r].y = v1[r] ? __builtin_fma(t, bv[c][r][1], w[r].y) : w[r].y;
+        }
+      }
+    }
+  };
+  double b0[2][kR][2];
+  load_b(0, b0);
+#pragma unroll
+  for (int r = 0; r < kR / 2; ++r) {
+    const int64_t e = t0 + lo[r];
+    const int q = (int)e;   // (plane 0: the internal index is the in-plane one)
+    double y00, y01, y10, y11;
+    op_br2<TB, HL>(a, o, x, hl, e, q, true, y00, y01);
+    op_br2<TB, HL>(a, o, x, hl, v1[r] ? e + 1 : e, v1[r] ? q + 1 : q, v1[r], y10, y11);
+    w[r] = make_double2(y00, v1[r] ? y10 : 0.0);
+    w[r + kR / 2] = make_double2(y01, v1[r] ? y11 : 0.0);
+  }
+  add_b(0, b0);
+  for (int c0 = 2; c0 < a.pb; c0 += 2) {
+    double bv[2][kR][2];
+    load_b(c0, bv);
+    add_b(c0, bv);
+  }
+}
+
 // ---- the augmented tail (workgroup 0) -----------------------------------------
 // The p tail entries of every vector are handled column-parallel: lane i of
 // wave 0 takes basis column i (and i + 64), so the work is one memory round
@@ -652,10 +786,11 @@ __device__ inline void load_chunk(const TB* V, int64_t ld, int64_t t0, int i0, i
 // the next phase's update, which then needs neither from the basis: w is not
 // stored.  XL (with KEEP): the update of this phase has left x_j in the x
 // half, so the stencil and the inner products read it from LDS.
-template <typename TB, bool HL, bool KEEP, bool XL>
+template <typename TB, bool HL, bool KEEP, bool XL, bool JT = false>
 __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Args& a, int jj, double* sacc, double* hl,
                                                         double* prow, double* own) {
   static_assert(KEEP || !XL, "x_j is in LDS only where the pass keeps x_j and w");
+  static_assert(!(JT && KEEP), "the joint two-species tiles keep nothing on chip");
   TB* V = reinterpret_cast<TB*>(a.V);
   const int64_t ld = a.ld;
   const int lane = kp_tid() & 63, wv = kp_tid() >> 6;
@@ -672,7 +807,8 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
   __syncthreads();
   double sxx = 0.0, sxw = 0.0, sww = 0.0;
   double2 kx[KEEP && !XL ? kR : 1], kw[KEEP ? kR : 1];   // (with XL, x_j stays where it is)
-  const int ns = num_segs(a);
+  // (JT: the Brusselator's two planes in joint sub-tiles over plane 0's rows)
+  const int ns = JT ? 1 : num_segs(a);
   for (int si = 0; si < ns; ++si) {
     const Seg sg = seg_at(a, o, si);
     const int64_t pend = (sg.end + 1) >> 1;
@@ -683,11 +819,14 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
 #pragma unroll
     for (int c = 0; c < kPMax; ++c)
       tc[c] = (c < a.pb) ? rnd<TB>(cload(a.tx + toff + c)) * inv_mu : 0.0;
-    for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * kR) {
+    for (int64_t q0 = sg.beg >> 1; q0 < pend; q0 += (int64_t)kThreads * (JT ? kR / 2 : kR)) {
       const int64_t t0 = 2 * q0;
       uint32_t lo[kR];
       bool ok[kR];
-      tile_pairs(q0, pend, lo, ok);
+      if constexpr (JT)
+        tile_pairs_joint(q0, pend, a.npt_pad, lo, ok);
+      else
+        tile_pairs(q0, pend, lo, ok);
       double2 xv[kR], wv2[kR];
       constexpr int CC = Raw<TB>::kCols;
       typename Raw<TB>::type va[CC][kR], vb[CC][kR];
@@ -701,7 +840,10 @@ __device__ __attribute__((always_inline)) inline void matvec_dots_pass(const Arg
       } else {
 #pragma unroll
         for (int r = 0; r < kR; ++r) xv[r] = xc.pair(t0 + lo[r]);
-        aug_tile<TB, HL>(a, o, sg, xc, hh, t0, lo, tc, wv2);
+        if constexpr (JT)
+          aug_tile_br2<TB, HL>(a, o, sg, xc, hh, t0, lo, tc, wv2);
+        else
+          aug_tile<TB, HL>(a, o, sg, xc, hh, t0, lo, tc, wv2);
       }
 #pragma unroll
       for (int r = 0; r < kR; ++r) {

@@ -57,6 +57,12 @@ static_assert(kLdsDoubles >= 2 * kNmPad * kNmPad, "the small exponential does no
 // identical in every workgroup); nxt: the leader's control of the next phase;
 // ok: cleared when a bounded wait gives up (the launch is aborting).  On
 // return cur holds the control of the next phase.
+// The Brusselator's matvec pass takes both species of a grid point together
+// (joint sub-tiles) with a float basis; with a float64 one the joint tile's
+// extra registers spill and cost what the shared loads save (measured), so it
+// keeps one plane at a time.
+template <typename TB> constexpr bool kJointBr = sizeof(TB) == 4;
+
 template <typename TB, bool MS>
 __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, double* lds, LeadLds& L, Ctl& cur, Ctl& nxt, int& ok,
                           int& kept, unsigned k) {
@@ -108,6 +114,10 @@ __device__ __attribute__((always_inline)) inline void run_phase(const Args& a, d
           matvec_dots_pass<TB, true, true, true>(a, c.j, sacc, hl, prow, mine);
         else if (a.keep_xw)
           matvec_dots_pass<TB, true, true, false>(a, c.j, sacc, hl, prow, mine);
+        else if (kJointBr<TB> && a.kind == KP_OP_BRUSSELATOR && !a.tangent && a.halo_lds)
+          matvec_dots_pass<TB, true, false, false, kJointBr<TB>>(a, c.j, sacc, hl, prow, mine);
+        else if (kJointBr<TB> && a.kind == KP_OP_BRUSSELATOR && !a.tangent)
+          matvec_dots_pass<TB, false, false, false, kJointBr<TB>>(a, c.j, sacc, hl, prow, mine);
         else if (a.halo_lds)
           matvec_dots_pass<TB, true, false, false>(a, c.j, sacc, hl, prow, mine);
         else
@@ -294,6 +304,15 @@ __device__ inline void init_problem(const Args& a, int m_target, int nflags) {
   st->mu = 1.0;
   st->err_max = st->omega = st->err = st->last_nrm2 = st->omega_prev = 0.0;
 }
+
+// The one-reduction float64 kernel (the main call's) is instantiated first, so
+// that it leads the code object and its placement does not move when the
+// other kernels change size (its run time varied by about 1 % with placement
+// alone, with identical instructions).
+template __global__ void k_run<double, false>(Args, int);
+template __global__ void k_run<float, false>(Args, int);
+template __global__ void k_run<double, true>(Args, int);
+template __global__ void k_run<float, true>(Args, int);
 
 __global__ __launch_bounds__(256) void k_init(Args a, int m_target) {
   init_problem(a, m_target, a.nwg * kFlagStride);
