@@ -657,7 +657,9 @@ def main():
                                                     out=o3), 3)))
             ys[basis] = o3.double().cpu().numpy().copy()
             c3.close()
-            byts = basis_bytes_per_call(sch3, p3.p, 2, p3.op.n, sz)
+            # (the two fields U and W, npt = N/2 elements each, are one
+            # N-vector of coefficient data per matvec: c = 1)
+            byts = basis_bytes_per_call(sch3, p3.p, 1, p3.op.n, sz)
             leg[basis] = {"ms_per_call": round(ms3, 3), "arnoldi_steps": inf3["arnoldi_steps"],
                           "substeps": inf3["substeps"], "rejected": inf3["rejected"],
                           "arnoldi_steps_per_s": round(inf3["arnoldi_steps"] / (ms3 * 1e-3), 1),
