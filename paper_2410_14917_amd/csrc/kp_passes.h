@@ -177,7 +177,7 @@ __device__ inline void copy_state(const Args& a, const Rows& o, TB* col0) {
 
 constexpr int kR = 4;    // element pairs per thread per sub-tile
 constexpr int kCh = 2;   // basis columns per chunk of the inner-product loop
-constexpr int kCu = 8;   // basis columns per chunk of the linear combinations
+constexpr int kCu = 4;   // basis columns per chunk of the linear combinations
 
 // Element offsets of this lane's kR pairs in the sub-tile that starts at
 // element 2*q0 (lane offsets stay below 2 * kThreads * kR, so every column

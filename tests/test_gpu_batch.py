@@ -163,7 +163,9 @@ def test_batched_rejects_overlapping_outputs():
 def test_full_size_uneven_batch_against_closed_form():
     """512 advection-diffusion-reaction problems, sides U{32..512}
     (N 1,024 .. 262,144, sum ~5.0e7), p = 3, h = 0.05, m <= 48, tol 1e-8, in
-    one batched call; every problem against the DFT closed form.  A second
+    one batched call; every problem against one plain call of its own (the
+    same controller, so within the float64 tolerance) and against the DFT
+    closed form.  A second
     call (a graph replay) gives the same bits: free teams take problems of
     other classes at run time, but a problem keeps its planned row partition
     whichever team solves it."""
@@ -180,6 +182,15 @@ def test_full_size_uneven_batch_against_closed_form():
         ndiff = sum(int(not torch.equal(y, y2)) for y, y2 in zip(ys, ys2))
     say(f"full-size batch: problems differing between two calls: {ndiff}")
     assert ndiff == 0
+    say("full-size batch: against one plain call per problem")
+    with kp.Context() as ctx:
+        worst_single = 0.0
+        for q, o, B, y in zip(probs, ops, Bs, ys):
+            y1 = ctx.phi_combo(o, B, q.h, tol=1e-8, m_max=48)
+            worst_single = max(worst_single, float(torch.linalg.vector_norm(y - y1) /
+                                                   torch.linalg.vector_norm(y1)))
+    say(f"  worst rel difference batched vs single calls {worst_single:.2e}")
+    assert worst_single <= FP64_TOL
     say("full-size batch: closed forms")
     worst, steps = 0.0, 0
     for q, y, inf in zip(probs, ys, infos):
