@@ -331,6 +331,35 @@ def test_fp32_basis_fixed_schedule(case):
     assert e_ref <= FP32_TOL and e_64 <= FP32_TOL
 
 
+# The FP32-basis Brusselator pass takes both species of a grid point together
+# (joint sub-tiles): the geometries that reach its other branches.
+FP32_BRUSSELATOR = [
+    (63, 41, 3, False),    # odd row width: pairs across rows, a padding element per plane; p = 3
+    (2051, 4, 1, False),   # rows too wide for the LDS halo copy: coherent halo loads
+    (130, 97, 2, True),    # the transposed operator, several workgroups
+    (64, 48, 0, False),    # p = 0: no columns of B in the matvec
+]
+
+
+@pytest.mark.parametrize("case", FP32_BRUSSELATOR)
+def test_fp32_basis_brusselator_joint_tiles(case):
+    nx, ny, p, tr = case
+    say(f"fp32 basis brusselator joint tiles {nx}x{ny} p={p} transpose={tr}")
+    pr = W.random_problem(33, kind=W.OP_BRUSSELATOR, nx=nx, ny=ny, p=p, h=0.02, nu=0.02)
+    opn = pr.op.with_transpose() if tr else pr.op
+    op = kp.Operator.from_host(opn)
+    B = torch.as_tensor(np.ascontiguousarray(pr.B[:, :p + 1].T), device="cuda")
+    with kp.Context(basis="f32", fixed_m=24, fixed_substeps=2) as ctx:
+        y, info = ctx.phi_combo(op, B, pr.h, m_max=24, info=True)
+    ref, _ = krylov.phi_combo(opn, pr.B[:, :p + 1], pr.h, p, fixed_m=24, fixed_substeps=2,
+                              m_max=24)
+    e = rel(y.cpu().numpy(), ref)
+    ea = float(np.max(np.abs(y.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    say(f"  rel err vs oracle {e:.2e}, max-abs {ea:.2e}")
+    assert info["status"] == 0 and info["substeps"] == 2
+    assert e <= FP32_TOL and ea <= FP32_TOL
+
+
 def test_fp32_basis_adaptive_brusselator():
     """Brusselator Jacobian (the FP32-basis workload's operator, small grid),
     adaptive, tol 1e-6."""
