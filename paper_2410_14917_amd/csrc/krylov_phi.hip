@@ -839,6 +839,7 @@ int build_args(const kp_ctx* ctx, const kp_op* A, const double* B, int p, int64_
   r.ny = A->ny;
   r.nplanes = nplanes;
   r.npt_pad = (npt + kp::kPlaneAlign - 1) / kp::kPlaneAlign * kp::kPlaneAlign;
+  if (nplanes == 2) r.npt_pad += kp::kPlaneSkew;
   r.tail_off = r.npt_pad * nplanes;
   r.ld = r.tail_off + kp::kTailPad;
   r.kind = A->kind;
