@@ -54,7 +54,7 @@ constexpr int kPlaneAlign = 128;          // plane offset alignment (elements)
 // rounded plane size, so that the two planes' elements at one grid point
 // (which the joint matvec tiles read together) are not a power of two apart
 // in memory (2048^2 planes otherwise sit exactly 2^22 elements apart; 17
-// alignment units measured best of 9..129: 1.5-2.5 % on the 2 x 2048^2 call).
+// alignment units measured best of 9..129: 2.6 % on the 2 x 2048^2 call).
 constexpr int kPlaneSkew = 17 * kPlaneAlign;
 
 // Phases of one call (uniform across the grid).
