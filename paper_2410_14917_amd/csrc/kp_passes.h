@@ -178,6 +178,9 @@ __device__ inline void copy_state(const Args& a, const Rows& o, TB* col0) {
 constexpr int kR = 4;    // element pairs per thread per sub-tile
 constexpr int kCh = 2;   // basis columns per chunk of the inner-product loop
 constexpr int kCu = 4;   // basis columns per chunk of the linear combinations
+// ... per basis type: a float basis takes two columns per chunk (measured over
+// 1, 2, 3, 4 and 6: two fastest), a float64 one kCu
+template <typename TB> constexpr int kCuOf = sizeof(TB) == 4 ? 2 : kCu;
 
 // Element offsets of this lane's kR pairs in the sub-tile that starts at
 // element 2*q0 (lane offsets stay below 2 * kThreads * kR, so every column
@@ -964,8 +967,8 @@ __device__ __attribute__((always_inline)) inline void update_pass(const Args& a,
           acc[r] = make_double2(cw * w.x, cw * w.y);
         }
       }
-      for (; i1 >= 0; i1 -= kCu)
-        axpy_cols<TB, kCu>(V, ld, t0, i1, -1, min(kCu, i1 + 1), coef, lo, acc);
+      for (; i1 >= 0; i1 -= kCuOf<TB>)
+        axpy_cols<TB, kCuOf<TB>>(V, ld, t0, i1, -1, min(kCuOf<TB>, i1 + 1), coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         const double y0 = rnd<TB>(acc[r].x), y1 = rnd<TB>(acc[r].y);
@@ -1007,8 +1010,8 @@ __device__ __attribute__((always_inline)) inline void combine_pass(const Args& a
       double2 acc[kR];
 #pragma unroll
       for (int r = 0; r < kR; ++r) acc[r] = make_double2(0.0, 0.0);
-      for (int i0 = 0; i0 < m; i0 += kCu)
-        axpy_cols<TB, kCu>(V, ld, t0, i0, 1, min(kCu, m - i0), coef, lo, acc);
+      for (int i0 = 0; i0 < m; i0 += kCuOf<TB>)
+        axpy_cols<TB, kCuOf<TB>>(V, ld, t0, i0, 1, min(kCuOf<TB>, m - i0), coef, lo, acc);
 #pragma unroll
       for (int r = 0; r < kR; ++r) {
         if (ok[r]) {
