@@ -177,7 +177,7 @@ __device__ inline void copy_state(const Args& a, const Rows& o, TB* col0) {
 
 constexpr int kR = 4;    // element pairs per thread per sub-tile
 constexpr int kCh = 2;   // basis columns per chunk of the inner-product loop
-constexpr int kCu = 4;   // basis columns per chunk of the linear combinations
+constexpr int kCu = 5;   // basis columns per chunk of the linear combinations
 // ... per basis type: a float basis takes two columns per chunk (measured over
 // 1, 2, 3, 4 and 6: two fastest), a float64 one kCu
 template <typename TB> constexpr int kCuOf = sizeof(TB) == 4 ? 2 : kCu;
